@@ -1,0 +1,229 @@
+/*
+ * addock -- MI355X-native docking hot path behind a C ABI.
+ *
+ * The library evaluates the AutoDock4-form scoring function with its
+ * analytic gradient on the GPU and drives the Lamarckian GA with ADADELTA
+ * local search built on it.  Its calls follow the paper's statement of the
+ * screening problem (Sec. 2.2 of "GPU-Accelerated Drug Discovery with Docking
+ * on the Summit Supercomputer"): many ligands are docked against one
+ * receptor whose grid maps are sent to the GPU once and stay resident
+ * (Sec. 2.2.1, Sec. 2.2.3); each ligand uses the maps of its own atom types
+ * (Sec. 2.2.3); each ligand gets nrun independent LGA runs, each with its own
+ * final pose and an evaluation cap nev, and the screen keeps the best run
+ * (Sec. 1.1).
+ *
+ * Conventions for every call:
+ *   - Return AD_OK (0) or a negative AD_E_* code; the message of the last
+ *     failure on a context is available from ad_last_error().
+ *   - Inputs are read during the call and never retained; outputs go to
+ *     caller buffers.  With ptrs_on_device != 0, genotype / energy / gradient
+ *     pointers are device pointers of the context's device and the call is
+ *     asynchronous on the context's stream; otherwise they are host pointers,
+ *     the library stages them and the call returns when the results are in
+ *     the caller's buffers.
+ *   - Calls on one context are serialised on its stream (the analogue of the
+ *     paper's one-at-a-time GPU section, Sec. 2.2.2).  A context must not be
+ *     used from two threads at once.
+ *   - Coordinates are in Angstrom, energies in kcal/mol, angles in radians.
+ *   - All numerical work runs in the library's HIP kernels.
+ */
+#ifndef ADDOCK_H
+#define ADDOCK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define AD_OK 0
+#define AD_E_INVALID -1     /* malformed argument (sizes, topology, values) */
+#define AD_E_NOMAP -2       /* a ligand atom type has no resident map */
+#define AD_E_OOM -3         /* device or host allocation failed */
+#define AD_E_DEVICE -4      /* no usable GPU / bad device index */
+#define AD_E_STATE -5       /* call order (e.g. scoring before a grid is loaded) */
+#define AD_E_UNSUPPORTED -6 /* option not implemented */
+#define AD_E_HIP -7         /* HIP runtime error */
+
+#define AD_MAX_TYPES 16
+#define AD_MAX_ATOMS 128
+#define AD_MAX_TORSIONS 32
+#define AD_GENO_STRIDE 40   /* genotype / gradient floats per pose */
+#define AD_MAX_POP 4096
+
+typedef struct ad_ctx ad_ctx;
+typedef struct ad_batch ad_batch;
+
+/* Force-field table (AutoDock4 functional form, Sec. 1).  Per type: radius
+ * R_ii and well depth eps_ii of the 12-6 term, atomic volume V, solvation
+ * parameter solpar, H-bond role (0 none, 1 donor, 2 acceptor) and, for
+ * acceptors, the 12-10 H-bond radius R_hb and depth eps_hb.  Scalars: term
+ * weights, Coulomb constant, Mehler-Solmajer dielectric (A, eps0, lambda,
+ * k), desolvation sigma and charge factor qasp, smoothing band width,
+ * map cutoff, affinity-map cap, distance floor and out-of-grid restraint
+ * constant.  Copied by ad_create. */
+typedef struct {
+  int n_types;
+  double Rii[AD_MAX_TYPES], epsii[AD_MAX_TYPES], vol[AD_MAX_TYPES], solpar[AD_MAX_TYPES];
+  double Rhb[AD_MAX_TYPES], epshb[AD_MAX_TYPES];
+  int hbrole[AD_MAX_TYPES];
+  double w_vdw, w_hb, w_el, w_sol, w_tor;
+  double coulomb, diel_A, diel_eps0, diel_lambda, diel_k;
+  double sigma, qasp, smooth, cutoff, cap, r_floor, k_out;
+} ad_forcefield;
+
+/* Grid geometry: nx*ny*nz points (each >= 2), node (i,j,k) at
+ * origin + spacing*(i,j,k).  map_types[m] is the force-field type of
+ * affinity map m (n_maps of them, distinct, each < n_types). */
+typedef struct {
+  int nx, ny, nz;
+  double spacing;
+  double origin[3];
+  int n_maps;
+  const int *map_types;
+} ad_grid_desc;
+
+/* One ligand: n_atoms (1..128) atoms with force-field type ids, partial
+ * charges and reference coordinates ([n_atoms][3]); n_bonds = n_atoms-1
+ * bonds ([n_bonds][2] atom indices) forming a tree; rotatable[b] != 0 marks
+ * bond b as a torsion.  Torsion k of the genotype is the k-th rotatable bond
+ * in bond order. */
+typedef struct {
+  int n_atoms, n_bonds;
+  const int *type_id;
+  const float *charge;
+  const float *xyz;
+  const int *bonds;
+  const unsigned char *rotatable;
+} ad_ligand;
+
+/* ---- context ----------------------------------------------------------
+ * ad_create: binds a context to GPU `device`, copies the force field and
+ * creates (hip_stream == NULL) or borrows (e.g. PyTorch's current stream)
+ * the stream all work is queued on.  No GPU -> AD_E_DEVICE; malformed force
+ * field -> AD_E_INVALID.  Device memory is owned by the context and freed by
+ * ad_destroy (which first waits for the stream). */
+int ad_create(ad_ctx **out, int device, const ad_forcefield *ff, void *hip_stream);
+void ad_destroy(ad_ctx *ctx);
+const char *ad_last_error(const ad_ctx *ctx);
+int ad_set_stream(ad_ctx *ctx, void *hip_stream);
+/* Waits for all work queued on the context's stream. */
+int ad_synchronize(ad_ctx *ctx);
+
+/* ---- receptor grids (Sec. 2.2.1, 2.2.3, 2.3) ----------------------------
+ * ad_load_grids: maps are FP32 [n_maps+2][nz][ny][nx], x fastest: the
+ * n_maps affinity maps in map_types order, then the electrostatic map, then
+ * the desolvation map.  A ligand atom of type t and charge q scores
+ * map_t + q*map_elec + |q|*map_desolv, interpolated trilinearly; outside the
+ * box the coordinate is clamped to the nearest face and
+ * k_out*|x - x_clamped|^2 is added.  The library copies the maps (host or
+ * device source) and keeps them resident until the next load or destroy.
+ * Errors: AD_E_INVALID (dims < 2, spacing <= 0, bad map types, non-finite
+ * values), AD_E_OOM. */
+int ad_load_grids(ad_ctx *ctx, const ad_grid_desc *g, const float *maps, int ptrs_on_device);
+
+/* ad_build_grids: computes the maps on the GPU from receptor atoms (host
+ * arrays: xyz [n_rec][3], type ids, charges) by direct sums in the same
+ * AutoDock4 form -- affinity map of type t: 12-6/12-10 plus the
+ * type-dependent desolvation half within `cutoff`, capped at `cap`;
+ * electrostatic map without cutoff; desolvation map qasp-part within
+ * `cutoff` -- and makes them resident as ad_load_grids would.  If maps_out
+ * is non-NULL the maps are also copied to that host buffer (layout as
+ * above).  Errors as ad_load_grids. */
+int ad_build_grids(ad_ctx *ctx, const ad_grid_desc *g, int n_rec, const float *rec_xyz, const int *rec_type,
+                   const float *rec_charge, float *maps_out);
+
+/* ---- ligands -------------------------------------------------------------
+ * ad_ligand_check: host-only validation of one ligand against a force
+ * field with n_types types (no context or GPU needed).  Returns AD_OK or
+ * AD_E_INVALID with a message in msg (if msg_len > 0). */
+int ad_ligand_check(const ad_ligand *lig, int n_types, char *msg, int msg_len);
+
+/* ad_load_ligands: validates every ligand (a tree; every rotatable bond
+ * between two non-terminal atoms; <= 128 atoms, <= 32 torsions; finite
+ * data), prepares its torsion tree and intramolecular pair list (atoms in
+ * different rigid fragments at bond distance >= 4) and uploads the batch.
+ * Needs loaded grids (AD_E_STATE otherwise); AD_E_NOMAP if an atom type has
+ * no map.  The batch belongs to the caller until ad_free_batch, and stays
+ * valid across grid reloads that keep the map types. */
+int ad_load_ligands(ad_ctx *ctx, int n, const ad_ligand *ligs, ad_batch **out);
+void ad_free_batch(ad_batch *b);
+/* Per-ligand sizes: atoms, torsions, intramolecular pairs, rigid fragments. */
+int ad_batch_info(const ad_batch *b, int lig, int *n_atoms, int *n_torsions, int *n_pairs, int *n_fragments);
+
+/* ---- scoring: the hot path ----------------------------------------------
+ * ad_score_poses: for pose p, ligand lig_idx[p] of the batch and genotype
+ * genotypes[p*40 + ...] = [t(3) | q(4: w,x,y,z) | theta(T)] (q need not be
+ * unit; it is normalised first; slots past 7+T are ignored):
+ *   pose: each torsion turns its leaf-side atoms by theta_k about its bond
+ *   (root side -> leaf side, right-handed), deepest torsion first; then
+ *   x = R(q)(y - c) + t, c the reference centroid.
+ *   energy[p] = inter (maps + restraint) + intramolecular pair energy.
+ *   grad (optional, [n][40]) = [dE/dt(3) | dE/domega(3) | 0 | dE/dtheta(T) |
+ *   0...], omega a world-frame rotation vector applied as
+ *   q <- exp(omega/2) q.
+ *   terms (optional, [n][3]) = {inter, intra, score = inter + w_tor*T}.
+ * Pure and deterministic.  A non-finite genotype gives NaN outputs (not an
+ * error).  Errors: AD_E_INVALID (bad lig_idx, n < 0), AD_E_STATE. */
+int ad_score_poses(ad_ctx *ctx, const ad_batch *b, int n, const int *lig_idx, const float *genotypes,
+                   float *energy, float *grad, float *terms, int ptrs_on_device);
+
+/* ---- docking: Lamarckian GA + ADADELTA (Sec. 1, Sec. 1.1) ----------------
+ * Per ligand, nrun independent runs.  Generation 0 evaluates pop random
+ * individuals (t uniform in the grid box, uniform random orientation,
+ * torsions uniform in [-pi, pi)); every later generation keeps the best
+ * individual, fills the rest by binary tournaments (win probability tour_p),
+ * two-point crossover over gene blocks (cx_rate) and per-slot mutation
+ * (mut_rate; +-mut_t A, +-mut_rot rad about a random axis, +-mut_theta rad),
+ * evaluates the pop-1 children, then runs ADADELTA (rho, eps) for ls_iters
+ * evaluations on round(ls_rate*pop) distinct non-elite individuals and
+ * writes the best pose each finds back into the population.  A run stops
+ * before a generation that would pass max_evals evaluations or max_gens
+ * generations.  Random numbers: Philox4x32-10 keyed by seed, counter
+ * (ligand id, run, generation, individual/stream/word) -- a ligand's
+ * result depends only on (seed, its id, params). */
+typedef struct {
+  int nrun, pop, max_gens;
+  int64_t max_evals;
+  double ls_rate;
+  int ls_iters;
+  double cx_rate, mut_rate, tour_p;
+  double rho, eps;
+  double mut_t, mut_theta, mut_rot;
+  int ls_method;   /* 0 = ADADELTA (others: AD_E_UNSUPPORTED) */
+  int autostop;    /* must be 0 (AD_E_UNSUPPORTED otherwise) */
+} ad_dock_params;
+
+typedef struct {
+  float best_energy;                  /* lowest search energy over runs */
+  float best_score;                   /* inter + w_tor*T at that pose */
+  float best_genotype[AD_GENO_STRIDE];
+  int best_run;
+  int generations;                    /* generations per run */
+  int64_t evals;                      /* evaluations over all runs */
+} ad_dock_result;
+
+/* ad_dock_batch: docks every ligand of the batch.  lig_ids (optional, [n])
+ * gives each ligand's id for the random streams (default: batch index).
+ * out: [n_lig] results (host).  run_energy / run_genotype (optional, host):
+ * [n_lig][nrun] best energy and [n_lig][nrun][40] genotype of every run.
+ * Synchronous.  Errors: AD_E_INVALID (params), AD_E_UNSUPPORTED, AD_E_OOM,
+ * AD_E_STATE. */
+int ad_dock_batch(ad_ctx *ctx, const ad_batch *b, const ad_dock_params *p, uint64_t seed, const uint32_t *lig_ids,
+                  ad_dock_result *out, float *run_energy, float *run_genotype);
+
+/* ad_local_search: ADADELTA on n given poses (genotypes in/out, [n][40]):
+ * `iters` evaluations each; on return genotypes hold the best evaluated
+ * pose and energy its energy (Lamarckian write-back).  Uses p->rho, p->eps. */
+int ad_local_search(ad_ctx *ctx, const ad_batch *b, int n, const int *lig_idx, float *genotypes, float *energy,
+                    const ad_dock_params *p, int iters, int ptrs_on_device);
+
+/* Diagnostics: the initial population genotypes of generation 0 for
+ * (ligand, run), [pop][40] host, exactly as ad_dock_batch draws them. */
+int ad_initial_population(ad_ctx *ctx, const ad_batch *b, int lig, uint32_t lig_id, int run, int pop,
+                          uint64_t seed, float *genotypes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,370 @@
+"""Python binding of libaddock (C ABI in include/addock.h).
+
+Argument marshalling only: every numerical step runs in the library's HIP
+kernels.  Host arrays are numpy; device arrays are torch CUDA tensors (torch
+provides device memory and streams).  The library must be built
+(``build()``); loading fails loudly otherwise -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+LIB_PATH = os.path.join(HERE, "libaddock.so")
+SOURCES = ["csrc/prep.cpp", "csrc/api.cpp", "csrc/dock.cpp", "csrc/kernels.hip"]
+
+AD_OK, AD_E_INVALID, AD_E_NOMAP, AD_E_OOM, AD_E_DEVICE, AD_E_STATE, AD_E_UNSUPPORTED, AD_E_HIP = 0, -1, -2, -3, -4, -5, -6, -7
+ERR_NAMES = {0: "AD_OK", -1: "AD_E_INVALID", -2: "AD_E_NOMAP", -3: "AD_E_OOM", -4: "AD_E_DEVICE",
+             -5: "AD_E_STATE", -6: "AD_E_UNSUPPORTED", -7: "AD_E_HIP"}
+MAX_TYPES, STRIDE = 16, 40
+
+EXPORTS = ["ad_create", "ad_destroy", "ad_last_error", "ad_set_stream", "ad_synchronize", "ad_load_grids",
+           "ad_build_grids", "ad_ligand_check", "ad_load_ligands", "ad_free_batch", "ad_batch_info",
+           "ad_score_poses", "ad_dock_batch", "ad_local_search", "ad_initial_population"]
+
+
+def build(verbose: bool = False, arch: str = "gfx950") -> str:
+    """Compile libaddock.so in-tree with hipcc for gfx950 (always recompiles)."""
+    cmd = ["hipcc", f"--offload-arch={arch}", "-O3", "-std=c++17", "-fPIC", "-shared",
+           "-Wno-unused-result", "-Wno-unused-value",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+    cmd += [os.path.join(HERE, s) for s in SOURCES] + ["-o", LIB_PATH + ".tmp"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("hipcc failed:\n" + r.stderr[-4000:])
+    if verbose:
+        print(r.stderr)
+    os.replace(LIB_PATH + ".tmp", LIB_PATH)
+    return LIB_PATH
+
+
+class AddockError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class ForceField(C.Structure):
+    _fields_ = [("n_types", C.c_int)] + [
+        (k, C.c_double * MAX_TYPES) for k in ("Rii", "epsii", "vol", "solpar", "Rhb", "epshb")
+    ] + [("hbrole", C.c_int * MAX_TYPES)] + [
+        (k, C.c_double) for k in ("w_vdw", "w_hb", "w_el", "w_sol", "w_tor", "coulomb", "diel_A",
+                                  "diel_eps0", "diel_lambda", "diel_k", "sigma", "qasp", "smooth",
+                                  "cutoff", "cap", "r_floor", "k_out")]
+
+
+class GridDesc(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("spacing", C.c_double),
+                ("origin", C.c_double * 3), ("n_maps", C.c_int), ("map_types", C.POINTER(C.c_int))]
+
+
+class Ligand(C.Structure):
+    _fields_ = [("n_atoms", C.c_int), ("n_bonds", C.c_int), ("type_id", C.POINTER(C.c_int)),
+                ("charge", C.POINTER(C.c_float)), ("xyz", C.POINTER(C.c_float)),
+                ("bonds", C.POINTER(C.c_int)), ("rotatable", C.POINTER(C.c_ubyte))]
+
+
+class DockParams(C.Structure):
+    _fields_ = [("nrun", C.c_int), ("pop", C.c_int), ("max_gens", C.c_int), ("max_evals", C.c_int64),
+                ("ls_rate", C.c_double), ("ls_iters", C.c_int), ("cx_rate", C.c_double),
+                ("mut_rate", C.c_double), ("tour_p", C.c_double), ("rho", C.c_double), ("eps", C.c_double),
+                ("mut_t", C.c_double), ("mut_theta", C.c_double), ("mut_rot", C.c_double),
+                ("ls_method", C.c_int), ("autostop", C.c_int)]
+
+
+class DockResult(C.Structure):
+    _fields_ = [("best_energy", C.c_float), ("best_score", C.c_float),
+                ("best_genotype", C.c_float * STRIDE), ("best_run", C.c_int),
+                ("generations", C.c_int), ("evals", C.c_int64)]
+
+
+DEFAULT_DOCK = dict(nrun=4, pop=50, max_gens=50, max_evals=2**62, ls_rate=0.06, ls_iters=300, cx_rate=0.8,
+                    mut_rate=0.02, tour_p=0.6, rho=0.8, eps=1e-2, mut_t=2.0, mut_theta=np.pi / 2,
+                    mut_rot=np.pi / 2, ls_method=0, autostop=0)
+
+_lib = None
+
+
+def lib():
+    """Load libaddock.so (torch first, so that both share one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    try:
+        import torch  # noqa: F401  (loads the HIP runtime the library will bind to)
+    except ImportError:
+        pass
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run paper_2007_03678_amd.build() "
+                           "(or __graft_entry__.build()) first")
+    L = C.CDLL(LIB_PATH)
+    vp, ip, fp = C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_float)
+    L.ad_create.argtypes = [C.POINTER(vp), C.c_int, C.POINTER(ForceField), vp]
+    L.ad_destroy.argtypes = [vp]
+    L.ad_destroy.restype = None
+    L.ad_last_error.argtypes = [vp]
+    L.ad_last_error.restype = C.c_char_p
+    L.ad_set_stream.argtypes = [vp, vp]
+    L.ad_synchronize.argtypes = [vp]
+    L.ad_load_grids.argtypes = [vp, C.POINTER(GridDesc), vp, C.c_int]
+    L.ad_build_grids.argtypes = [vp, C.POINTER(GridDesc), C.c_int, fp, ip, fp, fp]
+    L.ad_ligand_check.argtypes = [C.POINTER(Ligand), C.c_int, C.c_char_p, C.c_int]
+    L.ad_load_ligands.argtypes = [vp, C.c_int, C.POINTER(Ligand), C.POINTER(vp)]
+    L.ad_free_batch.argtypes = [vp]
+    L.ad_free_batch.restype = None
+    L.ad_batch_info.argtypes = [vp, C.c_int, ip, ip, ip, ip]
+    L.ad_score_poses.argtypes = [vp, vp, C.c_int, vp, vp, vp, vp, vp, C.c_int]
+    L.ad_dock_batch.argtypes = [vp, vp, C.POINTER(DockParams), C.c_uint64, vp, C.POINTER(DockResult), fp, fp]
+    L.ad_local_search.argtypes = [vp, vp, C.c_int, vp, vp, vp, C.POINTER(DockParams), C.c_int, C.c_int]
+    L.ad_initial_population.argtypes = [vp, vp, C.c_int, C.c_uint32, C.c_int, C.c_int, C.c_uint64, fp]
+    _lib = L
+    return L
+
+
+# ---------------------------------------------------------------------------
+# marshalling helpers
+# ---------------------------------------------------------------------------
+def make_forcefield(ff: dict) -> ForceField:
+    s = ForceField()
+    s.n_types = ff["n_types"]
+    for k in ("Rii", "epsii", "vol", "solpar", "Rhb", "epshb", "hbrole"):
+        arr = getattr(s, k)
+        for i, v in enumerate(ff[k]):
+            arr[i] = v
+    for k in ("w_vdw", "w_hb", "w_el", "w_sol", "w_tor", "coulomb", "diel_A", "diel_eps0", "diel_lambda",
+              "diel_k", "sigma", "qasp", "smooth", "cutoff", "cap", "r_floor", "k_out"):
+        setattr(s, k, float(ff[k]))
+    return s
+
+
+def make_params(**kw) -> DockParams:
+    d = dict(DEFAULT_DOCK)
+    for k, v in kw.items():
+        if k in d:
+            d[k] = v
+    p = DockParams()
+    for k, v in d.items():
+        setattr(p, k, v)
+    return p
+
+
+def _np(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _is_device(a):
+    return hasattr(a, "is_cuda") and a.is_cuda
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    if hasattr(a, "data_ptr"):
+        return C.c_void_p(a.data_ptr())
+    return a.ctypes.data_as(C.c_void_p)
+
+
+class _LigandArrays:
+    """Keeps numpy arrays alive while an ad_ligand points at them."""
+
+    def __init__(self, lig):
+        self.types = _np(lig.types, np.int32)
+        self.q = _np(lig.charges, np.float32)
+        self.xyz = _np(lig.xyz, np.float32).reshape(-1)
+        self.bonds = _np(lig.bonds, np.int32).reshape(-1)
+        self.rot = _np(lig.rotatable, np.uint8)
+        s = Ligand()
+        s.n_atoms = len(self.types)
+        s.n_bonds = len(self.rot)
+        s.type_id = self.types.ctypes.data_as(C.POINTER(C.c_int))
+        s.charge = self.q.ctypes.data_as(C.POINTER(C.c_float))
+        s.xyz = self.xyz.ctypes.data_as(C.POINTER(C.c_float))
+        s.bonds = self.bonds.ctypes.data_as(C.POINTER(C.c_int)) if self.bonds.size else None
+        s.rotatable = self.rot.ctypes.data_as(C.POINTER(C.c_ubyte)) if self.rot.size else None
+        self.s = s
+
+
+def ad_ligand_check(lig, n_types: int):
+    """Host-only validation; returns (code, message)."""
+    a = _LigandArrays(lig)
+    buf = C.create_string_buffer(256)
+    rc = lib().ad_ligand_check(C.byref(a.s), n_types, buf, 256)
+    return rc, buf.value.decode()
+
+
+def _grid_desc(grid):
+    mt = (C.c_int * max(1, len(grid.map_types)))(*grid.map_types)
+    d = GridDesc()
+    d.nx, d.ny, d.nz = grid.n
+    d.spacing = grid.spacing
+    d.origin[:] = list(grid.origin)
+    d.n_maps = len(grid.map_types)
+    d.map_types = C.cast(mt, C.POINTER(C.c_int))
+    return d, mt
+
+
+class Batch:
+    def __init__(self, ctx, handle, n):
+        self.ctx = ctx
+        self.h = handle
+        self.n = n
+
+    def info(self, i):
+        a, t, p, f = C.c_int(), C.c_int(), C.c_int(), C.c_int()
+        rc = lib().ad_batch_info(self.h, i, C.byref(a), C.byref(t), C.byref(p), C.byref(f))
+        if rc:
+            raise AddockError(rc, "bad ligand index")
+        return dict(n_atoms=a.value, n_torsions=t.value, n_pairs=p.value, n_fragments=f.value)
+
+    def free(self):
+        if self.h:
+            lib().ad_free_batch(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Context:
+    """One addock context (ad_create) on `device`; stream None = own stream,
+    'torch' = the current torch stream."""
+
+    def __init__(self, ff: dict, device: int = 0, stream=None):
+        L = lib()
+        self.ff = make_forcefield(ff)
+        h = C.c_void_p()
+        if stream == "torch":
+            import torch
+            stream = torch.cuda.current_stream(device).cuda_stream
+        rc = L.ad_create(C.byref(h), device, C.byref(self.ff), C.c_void_p(stream) if stream else None)
+        if rc:
+            raise AddockError(rc, "ad_create failed")
+        self.h = h
+
+    def _check(self, rc):
+        if rc:
+            raise AddockError(rc, lib().ad_last_error(self.h).decode())
+
+    def ad_synchronize(self):
+        self._check(lib().ad_synchronize(self.h))
+
+    def ad_set_stream(self, stream):
+        self._check(lib().ad_set_stream(self.h, C.c_void_p(stream) if stream else None))
+
+    def ad_load_grids(self, grid, maps):
+        d, keep = _grid_desc(grid)
+        if _is_device(maps):
+            self._check(lib().ad_load_grids(self.h, C.byref(d), _ptr(maps), 1))
+        else:
+            m = _np(maps, np.float32)
+            self._check(lib().ad_load_grids(self.h, C.byref(d), _ptr(m), 0))
+
+    def ad_build_grids(self, grid, receptor, want_maps=False):
+        d, keep = _grid_desc(grid)
+        xyz = _np(receptor.xyz, np.float32).reshape(-1)
+        ty = _np(receptor.types, np.int32)
+        q = _np(receptor.charges, np.float32)
+        out = None
+        if want_maps:
+            nx, ny, nz = grid.n
+            out = np.empty((len(grid.map_types) + 2, nz, ny, nx), np.float32)
+        self._check(lib().ad_build_grids(self.h, C.byref(d), len(ty), xyz.ctypes.data_as(C.POINTER(C.c_float)),
+                                         ty.ctypes.data_as(C.POINTER(C.c_int)),
+                                         q.ctypes.data_as(C.POINTER(C.c_float)),
+                                         out.ctypes.data_as(C.POINTER(C.c_float)) if out is not None else None))
+        return out
+
+    def ad_load_ligands(self, ligs) -> Batch:
+        arrs = [_LigandArrays(l) for l in ligs]
+        arr = (Ligand * max(1, len(arrs)))(*[a.s for a in arrs])
+        h = C.c_void_p()
+        self._check(lib().ad_load_ligands(self.h, len(arrs), arr, C.byref(h)))
+        return Batch(self, h, len(arrs))
+
+    def ad_score_poses(self, batch, lig_idx, genotypes, grad=False, terms=False, out=None):
+        """Host (numpy) or device (torch CUDA) arrays.  Returns (energy, grad, terms)."""
+        if _is_device(genotypes):
+            import torch
+            n = genotypes.shape[0]
+            E = out["energy"] if out else torch.empty(n, dtype=torch.float32, device=genotypes.device)
+            G = (out["grad"] if out else torch.empty((n, STRIDE), dtype=torch.float32,
+                                                     device=genotypes.device)) if grad else None
+            T = (out["terms"] if out else torch.empty((n, 3), dtype=torch.float32,
+                                                      device=genotypes.device)) if terms else None
+            self._check(lib().ad_score_poses(self.h, batch.h, n, _ptr(lig_idx), _ptr(genotypes), _ptr(E),
+                                             _ptr(G), _ptr(T), 1))
+            return E, G, T
+        g = _np(genotypes, np.float32)
+        n = g.shape[0]
+        idx = _np(lig_idx, np.int32)
+        E = np.empty(n, np.float32)
+        G = np.empty((n, STRIDE), np.float32) if grad else None
+        T = np.empty((n, 3), np.float32) if terms else None
+        self._check(lib().ad_score_poses(self.h, batch.h, n, _ptr(idx), _ptr(g), _ptr(E), _ptr(G), _ptr(T), 0))
+        return E, G, T
+
+    def ad_local_search(self, batch, lig_idx, genotypes, params: DockParams, iters: int):
+        """Host arrays: returns (best genotypes, energies); device tensors are updated in place."""
+        if _is_device(genotypes):
+            import torch
+            n = genotypes.shape[0]
+            E = torch.empty(n, dtype=torch.float32, device=genotypes.device)
+            self._check(lib().ad_local_search(self.h, batch.h, n, _ptr(lig_idx), _ptr(genotypes), _ptr(E),
+                                              C.byref(params), iters, 1))
+            return genotypes, E
+        g = _np(genotypes, np.float32).copy()
+        n = g.shape[0]
+        idx = _np(lig_idx, np.int32)
+        E = np.empty(n, np.float32)
+        self._check(lib().ad_local_search(self.h, batch.h, n, _ptr(idx), _ptr(g), _ptr(E), C.byref(params),
+                                          iters, 0))
+        return g, E
+
+    def ad_dock_batch(self, batch, params: DockParams, seed: int, lig_ids=None, per_run=False):
+        n = batch.n
+        res = (DockResult * max(1, n))()
+        ids = _np(lig_ids, np.uint32) if lig_ids is not None else None
+        re = np.empty((n, params.nrun), np.float32) if per_run else None
+        rg = np.empty((n, params.nrun, STRIDE), np.float32) if per_run else None
+        self._check(lib().ad_dock_batch(self.h, batch.h, C.byref(params), seed, _ptr(ids), res,
+                                        re.ctypes.data_as(C.POINTER(C.c_float)) if per_run else None,
+                                        rg.ctypes.data_as(C.POINTER(C.c_float)) if per_run else None))
+        out = dict(best_energy=np.array([res[i].best_energy for i in range(n)], np.float32),
+                   best_score=np.array([res[i].best_score for i in range(n)], np.float32),
+                   best_genotype=np.array([list(res[i].best_genotype) for i in range(n)], np.float32),
+                   best_run=np.array([res[i].best_run for i in range(n)], np.int32),
+                   generations=np.array([res[i].generations for i in range(n)], np.int32),
+                   evals=np.array([res[i].evals for i in range(n)], np.int64))
+        if per_run:
+            out["run_energy"] = re
+            out["run_genotype"] = rg
+        return out
+
+    def ad_initial_population(self, batch, lig, lig_id, run, pop, seed):
+        g = np.empty((pop, STRIDE), np.float32)
+        self._check(lib().ad_initial_population(self.h, batch.h, lig, lig_id, run, pop, seed,
+                                                g.ctypes.data_as(C.POINTER(C.c_float))))
+        return g
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ad_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def create(ff: dict, device: int = 0, stream=None) -> Context:
+    return Context(ff, device, stream)

@@ -1,0 +1,118 @@
+// Internal data layout of the addock library (host and device).
+#pragma once
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/addock.h"
+
+namespace ad {
+
+constexpr int kWave = 64;
+constexpr int kMaxAtoms = AD_MAX_ATOMS;
+constexpr int kMaxTor = AD_MAX_TORSIONS;
+constexpr int kStride = AD_GENO_STRIDE;
+constexpr int kMaxTypes = AD_MAX_TYPES;
+
+// Per-ligand descriptor in device memory.
+struct LigDesc {
+  int n_atoms, n_tor, n_pairs, n_frag;
+  int atom_off;   // into the AtomGeo / AtomInfo arrays
+  int pair_off;   // into the PairRec array
+  int tor_off;    // into the TorRec array
+  int max_depth;  // longest chain of nested torsions
+};
+
+// Reference coordinates relative to the rotation centre (reference
+// centroid), in the internal atom order: depth first from the root atom, so
+// that every torsion's moving set is one contiguous index range.
+struct alignas(32) AtomGeo {
+  double y[3];
+  double pad;
+};
+
+struct alignas(16) AtomInfo {
+  int map;      // affinity map index of the atom's type
+  float q;      // partial charge
+  int owner;    // deepest torsion whose moving set holds the atom (-1: root fragment)
+  int type;     // force-field type
+};
+
+// Intramolecular pair: i, j (internal order) and type-pair index packed in
+// one word, with the two pair-specific coefficients precomputed in double
+// and rounded: qq = w_el k_e q_i q_j, dsv = w_sol (S_i V_j + S_j V_i).
+struct alignas(16) PairRec {
+  uint32_t ijt;   // i | j << 8 | (ti * n_types + tj) << 16
+  float qq;
+  float dsv;
+  float pad;
+};
+
+// Torsion: axis through o (reference frame, relative to the centre) with
+// unit direction u; parent torsion (-1: hangs off the root fragment);
+// moving set = internal atoms [s, e); root-side atom a and leaf-side atom b
+// (internal indices); 1/|y_b - y_a| (bond length is pose invariant).
+struct alignas(16) TorRec {
+  double o[3];
+  double u[3];
+  double inv_len;
+  int parent, s, e, a, b;
+  int depth;      // torsions on the path from the root, this one included
+};
+
+// 12-6 / 12-10 coefficients of a type pair (weights folded in).
+struct alignas(16) LJRec {
+  float A, B, r0, hb;   // hb = 1 for the 12-10 form
+};
+
+// Scalars of the functional form used inside the kernels.
+struct FFConst {
+  float diel_A, diel_B, diel_k, diel_lB_log2e;   // exp(-lambda B r) = exp2(-diel_lB_log2e r)
+  float ds_log2e;                                // exp(-r^2/(2 s^2)) = exp2(-ds_log2e r^2)
+  float inv_s2;                                  // 1/sigma^2
+  float diel_c1;                                 // k * B * (lambda B): elec derivative factor
+  float half_smooth, r_floor2;
+  float w_tor;
+  int n_types;
+  double k_out;
+};
+
+// Resident grid as seen by the kernels: per affinity map m one float4 per
+// node {map_m, elec, desolv, 0}, node-major [m][nz][ny][nx].
+struct GridArgs {
+  const float *maps;   // float4 records
+  int nx, ny, nz, n_maps;
+  double ox, oy, oz;
+  double h, inv_h;
+};
+
+// Device view of a ligand batch.
+struct BatchArgs {
+  const LigDesc *lig;
+  const AtomGeo *geo;
+  const AtomInfo *info;
+  const PairRec *pairs;
+  const TorRec *tors;
+  const LJRec *lj;       // [n_types * n_types]
+  int n_lig;
+  int n_types;
+};
+
+// Host-side prepared ligand (before upload).
+struct PreparedLigand {
+  int n_atoms = 0, n_tor = 0, n_frag = 0, max_depth = 0;
+  std::vector<AtomGeo> geo;
+  std::vector<AtomInfo> info;
+  std::vector<PairRec> pairs;
+  std::vector<TorRec> tors;
+  std::vector<int> perm;   // internal index -> input atom index
+};
+
+// Host preprocessing (prep.cpp).  type_to_map may be null (validation only).
+int prepare_ligand(const ad_ligand &L, const ad_forcefield &ff, const int *type_to_map, PreparedLigand *out,
+                   std::string *err);
+void build_lj_table(const ad_forcefield &ff, std::vector<LJRec> *out);
+FFConst make_ffconst(const ad_forcefield &ff);
+
+}  // namespace ad

@@ -1,0 +1,561 @@
+// C-ABI entry points of libaddock: argument validation, device memory,
+// host<->device staging and kernel launches on the context's stream.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "api_internal.h"
+
+using namespace ad;
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+int ad_ctx::fail(int code, const std::string &msg) {
+  err = msg;
+  return code;
+}
+
+int ad_ctx::hip_fail(hipError_t e, const char *where) {
+  err = std::string(where) + ": " + hipGetErrorString(e);
+  return AD_E_HIP;
+}
+
+#define HIP_TRY(ctx, expr)                                  \
+  do {                                                      \
+    hipError_t _e = (expr);                                 \
+    if (_e != hipSuccess) return (ctx)->hip_fail(_e, #expr); \
+  } while (0)
+
+void *ad_ctx::scratch_alloc(size_t bytes, int slot) {
+  // per-slot grow-only device buffers; calls on one context are serialised
+  if (slot < 0 || slot >= kScratchSlots) return nullptr;
+  bytes = (bytes + 255) & ~(size_t)255;
+  if (scratch_bytes[slot] >= bytes && scratch[slot]) return scratch[slot];
+  if (scratch[slot]) {
+    hipStreamSynchronize(stream);
+    hipFree(scratch[slot]);
+    scratch[slot] = nullptr;
+    scratch_bytes[slot] = 0;
+  }
+  void *p = nullptr;
+  if (hipMalloc(&p, std::max(bytes, (size_t)256)) != hipSuccess) return nullptr;
+  scratch[slot] = p;
+  scratch_bytes[slot] = bytes;
+  return p;
+}
+
+EvalConst ad_ctx::eval_const(const ad_batch *b) const {
+  EvalConst C;
+  C.ff = ffc;
+  C.grid.maps = maps4;
+  C.grid.nx = grid_n[0];
+  C.grid.ny = grid_n[1];
+  C.grid.nz = grid_n[2];
+  C.grid.n_maps = n_maps;
+  C.grid.ox = origin[0];
+  C.grid.oy = origin[1];
+  C.grid.oz = origin[2];
+  C.grid.h = spacing;
+  C.grid.inv_h = 1.0 / spacing;
+  C.batch.lig = b->lig;
+  C.batch.geo = b->geo;
+  C.batch.info = b->info;
+  C.batch.pairs = b->pairs;
+  C.batch.tors = b->tors;
+  C.batch.lj = lj_dev;
+  C.batch.n_lig = b->n_lig;
+  C.batch.n_types = ff.n_types;
+  return C;
+}
+
+static bool finite_d(double v) { return std::isfinite(v); }
+
+static int check_ff(const ad_forcefield *ff, std::string *msg) {
+  if (!ff) return *msg = "null force field", AD_E_INVALID;
+  if (ff->n_types < 1 || ff->n_types > AD_MAX_TYPES) return *msg = "n_types must be 1..16", AD_E_INVALID;
+  for (int t = 0; t < ff->n_types; ++t) {
+    if (!(ff->Rii[t] > 0) || !(ff->epsii[t] >= 0) || !finite_d(ff->vol[t]) || !finite_d(ff->solpar[t]) ||
+        ff->hbrole[t] < 0 || ff->hbrole[t] > 2 || !finite_d(ff->Rii[t]) || !finite_d(ff->epsii[t]))
+      return *msg = "bad per-type force-field value", AD_E_INVALID;
+    if (ff->hbrole[t] == 2 && (!(ff->Rhb[t] > 0) || !(ff->epshb[t] >= 0) || !finite_d(ff->Rhb[t])))
+      return *msg = "bad H-bond parameters", AD_E_INVALID;
+  }
+  const double s[] = {ff->w_vdw, ff->w_hb, ff->w_el, ff->w_sol, ff->w_tor, ff->coulomb, ff->diel_A, ff->diel_eps0,
+                      ff->diel_lambda, ff->diel_k, ff->sigma, ff->qasp, ff->smooth, ff->cutoff, ff->cap,
+                      ff->r_floor, ff->k_out};
+  for (double v : s)
+    if (!finite_d(v)) return *msg = "non-finite force-field scalar", AD_E_INVALID;
+  if (!(ff->sigma > 0) || !(ff->smooth >= 0) || !(ff->r_floor > 0) || !(ff->cutoff > 0) || !(ff->k_out >= 0))
+    return *msg = "bad force-field scalar", AD_E_INVALID;
+  return AD_OK;
+}
+
+static int check_grid_desc(const ad_grid_desc *g, int n_types, std::string *msg) {
+  if (!g) return *msg = "null grid descriptor", AD_E_INVALID;
+  if (g->nx < 2 || g->ny < 2 || g->nz < 2) return *msg = "grid needs >= 2 points per axis", AD_E_INVALID;
+  if ((double)g->nx * g->ny * g->nz > 2.0e9) return *msg = "grid too large", AD_E_INVALID;
+  if (!(g->spacing > 0) || !finite_d(g->spacing)) return *msg = "spacing must be > 0", AD_E_INVALID;
+  for (int d = 0; d < 3; ++d)
+    if (!finite_d(g->origin[d])) return *msg = "non-finite origin", AD_E_INVALID;
+  if (g->n_maps < 0 || g->n_maps > AD_MAX_TYPES) return *msg = "n_maps must be 0..16", AD_E_INVALID;
+  if (g->n_maps > 0 && !g->map_types) return *msg = "null map_types", AD_E_INVALID;
+  for (int m = 0; m < g->n_maps; ++m) {
+    if (g->map_types[m] < 0 || g->map_types[m] >= n_types) return *msg = "map type out of range", AD_E_INVALID;
+    for (int k = 0; k < m; ++k)
+      if (g->map_types[k] == g->map_types[m]) return *msg = "duplicate map type", AD_E_INVALID;
+  }
+  return AD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+extern "C" int ad_create(ad_ctx **out, int device, const ad_forcefield *ff, void *hip_stream) {
+  if (!out) return AD_E_INVALID;
+  *out = nullptr;
+  std::string msg;
+  int rc = check_ff(ff, &msg);
+  if (rc) return rc;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return AD_E_DEVICE;
+  if (device < 0 || device >= count) return AD_E_DEVICE;
+  if (hipSetDevice(device) != hipSuccess) return AD_E_DEVICE;
+  ad_ctx *c = new ad_ctx();
+  c->device = device;
+  c->ff = *ff;
+  c->ffc = make_ffconst(*ff);
+  if (hip_stream) {
+    c->stream = (hipStream_t)hip_stream;
+    c->own_stream = false;
+  } else {
+    if (hipStreamCreate(&c->stream) != hipSuccess) {
+      delete c;
+      return AD_E_HIP;
+    }
+    c->own_stream = true;
+  }
+  build_lj_table(*ff, &c->lj_host);
+  if (hipMalloc(&c->lj_dev, c->lj_host.size() * sizeof(LJRec)) != hipSuccess ||
+      hipMemcpy(c->lj_dev, c->lj_host.data(), c->lj_host.size() * sizeof(LJRec), hipMemcpyHostToDevice) !=
+          hipSuccess) {
+    ad_destroy(c);
+    return AD_E_OOM;
+  }
+  for (int t = 0; t < AD_MAX_TYPES; ++t) c->type_to_map[t] = -1;
+  *out = c;
+  return AD_OK;
+}
+
+extern "C" void ad_destroy(ad_ctx *c) {
+  if (!c) return;
+  hipSetDevice(c->device);
+  if (c->stream) hipStreamSynchronize(c->stream);
+  if (c->maps4) hipFree(c->maps4);
+  if (c->lj_dev) hipFree(c->lj_dev);
+  for (int s = 0; s < ad_ctx::kScratchSlots; ++s)
+    if (c->scratch[s]) hipFree(c->scratch[s]);
+  c->free_dock_buffers();
+  if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
+  delete c;
+}
+
+extern "C" const char *ad_last_error(const ad_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+extern "C" int ad_set_stream(ad_ctx *c, void *hip_stream) {
+  if (!c) return AD_E_INVALID;
+  hipSetDevice(c->device);
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (c->own_stream) hipStreamDestroy(c->stream);
+  if (hip_stream) {
+    c->stream = (hipStream_t)hip_stream;
+    c->own_stream = false;
+  } else {
+    HIP_TRY(c, hipStreamCreate(&c->stream));
+    c->own_stream = true;
+  }
+  return AD_OK;
+}
+
+extern "C" int ad_synchronize(ad_ctx *c) {
+  if (!c) return AD_E_INVALID;
+  hipSetDevice(c->device);
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return AD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// grids
+// ---------------------------------------------------------------------------
+static int set_grid_meta(ad_ctx *c, const ad_grid_desc *g) {
+  c->grid_n[0] = g->nx;
+  c->grid_n[1] = g->ny;
+  c->grid_n[2] = g->nz;
+  c->spacing = g->spacing;
+  for (int d = 0; d < 3; ++d) c->origin[d] = g->origin[d];
+  c->n_maps = g->n_maps;
+  for (int t = 0; t < AD_MAX_TYPES; ++t) c->type_to_map[t] = -1;
+  for (int m = 0; m < g->n_maps; ++m) {
+    c->map_types[m] = g->map_types[m];
+    c->type_to_map[g->map_types[m]] = m;
+  }
+  return AD_OK;
+}
+
+static int ensure_maps4(ad_ctx *c, size_t nn, int n_maps) {
+  size_t bytes = std::max((size_t)16, nn * (size_t)std::max(n_maps, 1) * 16);
+  if (c->maps4 && c->maps4_bytes >= bytes) return AD_OK;
+  if (c->maps4) {
+    hipStreamSynchronize(c->stream);
+    hipFree(c->maps4);
+    c->maps4 = nullptr;
+    c->maps4_bytes = 0;
+  }
+  if (hipMalloc(&c->maps4, bytes) != hipSuccess) return c->fail(AD_E_OOM, "cannot allocate grid maps");
+  c->maps4_bytes = bytes;
+  return AD_OK;
+}
+
+extern "C" int ad_load_grids(ad_ctx *c, const ad_grid_desc *g, const float *maps, int ptrs_on_device) {
+  if (!c) return AD_E_INVALID;
+  std::string msg;
+  int rc = check_grid_desc(g, c->ff.n_types, &msg);
+  if (rc) return c->fail(rc, msg);
+  if (!maps) return c->fail(AD_E_INVALID, "null maps");
+  hipSetDevice(c->device);
+  const size_t nn = (size_t)g->nx * g->ny * g->nz;
+  const size_t total = nn * (size_t)(g->n_maps + 2);
+  if (!ptrs_on_device) {
+    for (size_t i = 0; i < total; ++i)
+      if (!std::isfinite(maps[i])) return c->fail(AD_E_INVALID, "non-finite map value");
+  }
+  rc = ensure_maps4(c, nn, g->n_maps);
+  if (rc) return rc;
+  const float *src = maps;
+  if (!ptrs_on_device) {
+    float *tmp = (float *)c->scratch_alloc(total * sizeof(float), 0);
+    if (!tmp) return c->fail(AD_E_OOM, "cannot allocate staging buffer");
+    HIP_TRY(c, hipMemcpyAsync(tmp, maps, total * sizeof(float), hipMemcpyHostToDevice, c->stream));
+    src = tmp;
+  }
+  if (g->n_maps > 0) HIP_TRY(c, launch_relayout(src, c->maps4, nn, g->n_maps, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  set_grid_meta(c, g);
+  c->has_grid = true;
+  return AD_OK;
+}
+
+extern "C" int ad_build_grids(ad_ctx *c, const ad_grid_desc *g, int n_rec, const float *rec_xyz, const int *rec_type,
+                              const float *rec_charge, float *maps_out) {
+  if (!c) return AD_E_INVALID;
+  std::string msg;
+  int rc = check_grid_desc(g, c->ff.n_types, &msg);
+  if (rc) return c->fail(rc, msg);
+  if (n_rec < 0 || (n_rec > 0 && (!rec_xyz || !rec_type || !rec_charge)))
+    return c->fail(AD_E_INVALID, "bad receptor arrays");
+  for (int a = 0; a < n_rec; ++a) {
+    if (rec_type[a] < 0 || rec_type[a] >= c->ff.n_types) return c->fail(AD_E_INVALID, "receptor type out of range");
+    if (!std::isfinite(rec_charge[a]) || !std::isfinite(rec_xyz[3 * a]) || !std::isfinite(rec_xyz[3 * a + 1]) ||
+        !std::isfinite(rec_xyz[3 * a + 2]))
+      return c->fail(AD_E_INVALID, "non-finite receptor data");
+  }
+  hipSetDevice(c->device);
+  const size_t nn = (size_t)g->nx * g->ny * g->nz;
+  rc = ensure_maps4(c, nn, g->n_maps);
+  if (rc) return rc;
+  // receptor staging: xyz, type, charge in one scratch block
+  size_t o_xyz = 0, o_t = ((size_t)3 * n_rec * 4 + 255) & ~(size_t)255;
+  size_t o_q = o_t + (((size_t)n_rec * 4 + 255) & ~(size_t)255);
+  size_t o_args = o_q + (((size_t)n_rec * 4 + 255) & ~(size_t)255);
+  size_t bytes = o_args + ((map_build_args_size() + 255) & ~(size_t)255);
+  char *blk = (char *)c->scratch_alloc(bytes, 1);
+  if (!blk) return c->fail(AD_E_OOM, "cannot allocate receptor staging");
+  float *soa = nullptr;
+  if (maps_out) {
+    soa = (float *)c->scratch_alloc(nn * (size_t)(g->n_maps + 2) * sizeof(float), 0);
+    if (!soa) return c->fail(AD_E_OOM, "cannot allocate map output staging");
+  }
+  std::vector<char> hargs(map_build_args_size());
+  fill_map_build_args(hargs.data(), c->ff, g, n_rec, (const float *)(blk + o_xyz), (const int *)(blk + o_t),
+                      (const float *)(blk + o_q), c->maps4, soa);
+  if (n_rec > 0) {
+    HIP_TRY(c, hipMemcpyAsync(blk + o_xyz, rec_xyz, (size_t)3 * n_rec * 4, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(blk + o_t, rec_type, (size_t)n_rec * 4, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(blk + o_q, rec_charge, (size_t)n_rec * 4, hipMemcpyHostToDevice, c->stream));
+  }
+  HIP_TRY(c, hipMemcpyAsync(blk + o_args, hargs.data(), hargs.size(), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, launch_build_maps(reinterpret_cast<const MapBuildArgs *>(blk + o_args), nn, c->stream));
+  if (maps_out)
+    HIP_TRY(c, hipMemcpyAsync(maps_out, soa, nn * (size_t)(g->n_maps + 2) * sizeof(float), hipMemcpyDeviceToHost,
+                              c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  set_grid_meta(c, g);
+  c->has_grid = true;
+  return AD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// ligands
+// ---------------------------------------------------------------------------
+extern "C" int ad_ligand_check(const ad_ligand *lig, int n_types, char *msg, int msg_len) {
+  std::string err;
+  int rc;
+  if (!lig) {
+    rc = AD_E_INVALID;
+    err = "null ligand";
+  } else if (n_types < 1 || n_types > AD_MAX_TYPES) {
+    rc = AD_E_INVALID;
+    err = "n_types must be 1..16";
+  } else {
+    ad_forcefield ff;
+    memset(&ff, 0, sizeof(ff));
+    ff.n_types = n_types;
+    rc = prepare_ligand(*lig, ff, nullptr, nullptr, &err);
+  }
+  if (msg && msg_len > 0) {
+    strncpy(msg, rc ? err.c_str() : "", (size_t)msg_len - 1);
+    msg[msg_len - 1] = 0;
+  }
+  return rc;
+}
+
+extern "C" int ad_load_ligands(ad_ctx *c, int n, const ad_ligand *ligs, ad_batch **out) {
+  if (!c || !out) return AD_E_INVALID;
+  *out = nullptr;
+  if (n < 0 || (n > 0 && !ligs)) return c->fail(AD_E_INVALID, "bad ligand array");
+  if (!c->has_grid) return c->fail(AD_E_STATE, "load or build grids before ligands");
+  std::vector<PreparedLigand> prep(n);
+  for (int i = 0; i < n; ++i) {
+    std::string err;
+    int rc = prepare_ligand(ligs[i], c->ff, c->type_to_map, &prep[i], &err);
+    if (rc) return c->fail(rc, "ligand " + std::to_string(i) + ": " + err);
+  }
+  ad_batch *b = new ad_batch();
+  b->ctx = c;
+  b->device = c->device;
+  b->n_lig = n;
+  std::vector<LigDesc> lig(n);
+  std::vector<AtomGeo> geo;
+  std::vector<AtomInfo> info;
+  std::vector<PairRec> pairs;
+  std::vector<TorRec> tors;
+  int cap = 64;
+  for (int i = 0; i < n; ++i) {
+    const PreparedLigand &P = prep[i];
+    LigDesc &d = lig[i];
+    d.n_atoms = P.n_atoms;
+    d.n_tor = P.n_tor;
+    d.n_pairs = (int)P.pairs.size();
+    d.n_frag = P.n_frag;
+    d.atom_off = (int)geo.size();
+    d.pair_off = (int)pairs.size();
+    d.tor_off = (int)tors.size();
+    d.max_depth = P.max_depth;
+    geo.insert(geo.end(), P.geo.begin(), P.geo.end());
+    info.insert(info.end(), P.info.begin(), P.info.end());
+    pairs.insert(pairs.end(), P.pairs.begin(), P.pairs.end());
+    tors.insert(tors.end(), P.tors.begin(), P.tors.end());
+    if (P.n_atoms > 64) cap = 128;
+  }
+  b->cap = cap;
+  b->lig_host = lig;
+  for (int t = 0; t < AD_MAX_TYPES; ++t) b->map_of_type[t] = -1;
+  for (int i = 0; i < n; ++i)
+    for (int a = 0; a < ligs[i].n_atoms; ++a) b->map_of_type[ligs[i].type_id[a]] = c->type_to_map[ligs[i].type_id[a]];
+  hipSetDevice(c->device);
+  auto up = [&](void **dst, const void *src, size_t bytes) -> bool {
+    if (hipMalloc(dst, std::max(bytes, (size_t)256)) != hipSuccess) return false;
+    if (bytes && hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice) != hipSuccess) return false;
+    return true;
+  };
+  bool ok = up((void **)&b->lig, lig.data(), lig.size() * sizeof(LigDesc)) &&
+            up((void **)&b->geo, geo.data(), geo.size() * sizeof(AtomGeo)) &&
+            up((void **)&b->info, info.data(), info.size() * sizeof(AtomInfo)) &&
+            up((void **)&b->pairs, pairs.data(), pairs.size() * sizeof(PairRec)) &&
+            up((void **)&b->tors, tors.data(), tors.size() * sizeof(TorRec));
+  if (!ok) {
+    ad_free_batch(b);
+    return c->fail(AD_E_OOM, "cannot upload ligand batch");
+  }
+  *out = b;
+  return AD_OK;
+}
+
+extern "C" void ad_free_batch(ad_batch *b) {
+  if (!b) return;
+  hipSetDevice(b->device);
+  if (b->ctx && b->ctx->stream) hipStreamSynchronize(b->ctx->stream);
+  hipFree(b->lig);
+  hipFree(b->geo);
+  hipFree(b->info);
+  hipFree(b->pairs);
+  hipFree(b->tors);
+  delete b;
+}
+
+extern "C" int ad_batch_info(const ad_batch *b, int lig, int *n_atoms, int *n_torsions, int *n_pairs,
+                             int *n_fragments) {
+  if (!b || lig < 0 || lig >= b->n_lig) return AD_E_INVALID;
+  const LigDesc &d = b->lig_host[lig];
+  if (n_atoms) *n_atoms = d.n_atoms;
+  if (n_torsions) *n_torsions = d.n_tor;
+  if (n_pairs) *n_pairs = d.n_pairs;
+  if (n_fragments) *n_fragments = d.n_frag;
+  return AD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// scoring and local search
+// ---------------------------------------------------------------------------
+static int check_batch(ad_ctx *c, const ad_batch *b) {
+  if (!b) return c->fail(AD_E_INVALID, "null batch");
+  if (b->ctx != c) return c->fail(AD_E_INVALID, "batch belongs to another context");
+  if (!c->has_grid) return c->fail(AD_E_STATE, "no grid loaded");
+  // the batch's atoms carry map indices: the resident grid must still assign them
+  for (int t = 0; t < AD_MAX_TYPES; ++t)
+    if (b->map_of_type[t] >= 0 && c->type_to_map[t] != b->map_of_type[t])
+      return c->fail(AD_E_STATE, "grid maps changed since the batch was loaded; reload the ligands");
+  return AD_OK;
+}
+
+extern "C" int ad_score_poses(ad_ctx *c, const ad_batch *b, int n, const int *lig_idx, const float *genotypes,
+                              float *energy, float *grad, float *terms, int ptrs_on_device) {
+  if (!c) return AD_E_INVALID;
+  int rc = check_batch(c, b);
+  if (rc) return rc;
+  if (n < 0) return c->fail(AD_E_INVALID, "n < 0");
+  if (n == 0) return AD_OK;
+  if (!lig_idx || !genotypes || !energy) return c->fail(AD_E_INVALID, "null argument");
+  hipSetDevice(c->device);
+  const EvalConst C = c->eval_const(b);
+  if (ptrs_on_device) {
+    HIP_TRY(c, launch_score(C, b->cap, n, lig_idx, genotypes, energy, grad, terms, c->stream));
+    return AD_OK;
+  }
+  for (int p = 0; p < n; ++p)
+    if (lig_idx[p] < 0 || lig_idx[p] >= b->n_lig) return c->fail(AD_E_INVALID, "lig_idx out of range");
+  const size_t nb_idx = ((size_t)n * 4 + 255) & ~(size_t)255;
+  const size_t nb_geo = ((size_t)n * kStride * 4 + 255) & ~(size_t)255;
+  const size_t nb_e = ((size_t)n * 4 + 255) & ~(size_t)255;
+  const size_t nb_g = grad ? nb_geo : 0;
+  const size_t nb_t = terms ? (((size_t)n * 12 + 255) & ~(size_t)255) : 0;
+  char *blk = (char *)c->scratch_alloc(nb_idx + nb_geo + nb_e + nb_g + nb_t, 0);
+  if (!blk) return c->fail(AD_E_OOM, "cannot allocate staging");
+  int *d_idx = (int *)blk;
+  float *d_geo = (float *)(blk + nb_idx);
+  float *d_e = (float *)(blk + nb_idx + nb_geo);
+  float *d_g = grad ? (float *)(blk + nb_idx + nb_geo + nb_e) : nullptr;
+  float *d_t = terms ? (float *)(blk + nb_idx + nb_geo + nb_e + nb_g) : nullptr;
+  HIP_TRY(c, hipMemcpyAsync(d_idx, lig_idx, (size_t)n * 4, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(d_geo, genotypes, (size_t)n * kStride * 4, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, launch_score(C, b->cap, n, d_idx, d_geo, d_e, d_g, d_t, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(energy, d_e, (size_t)n * 4, hipMemcpyDeviceToHost, c->stream));
+  if (grad) HIP_TRY(c, hipMemcpyAsync(grad, d_g, (size_t)n * kStride * 4, hipMemcpyDeviceToHost, c->stream));
+  if (terms) HIP_TRY(c, hipMemcpyAsync(terms, d_t, (size_t)n * 12, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return AD_OK;
+}
+
+extern "C" int ad_local_search(ad_ctx *c, const ad_batch *b, int n, const int *lig_idx, float *genotypes,
+                               float *energy, const ad_dock_params *p, int iters, int ptrs_on_device) {
+  if (!c) return AD_E_INVALID;
+  int rc = check_batch(c, b);
+  if (rc) return rc;
+  if (n < 0 || iters < 0 || !p) return c->fail(AD_E_INVALID, "bad local-search arguments");
+  if (!(p->rho >= 0 && p->rho < 1) || !(p->eps > 0)) return c->fail(AD_E_INVALID, "bad ADADELTA rho / eps");
+  if (n == 0) return AD_OK;
+  if (!lig_idx || !genotypes || !energy) return c->fail(AD_E_INVALID, "null argument");
+  hipSetDevice(c->device);
+  const EvalConst C = c->eval_const(b);
+  if (ptrs_on_device) {
+    HIP_TRY(c, launch_local_search(C, b->cap, n, lig_idx, genotypes, energy, iters, p->rho, p->eps, c->stream));
+    return AD_OK;
+  }
+  for (int q = 0; q < n; ++q)
+    if (lig_idx[q] < 0 || lig_idx[q] >= b->n_lig) return c->fail(AD_E_INVALID, "lig_idx out of range");
+  const size_t nb_idx = ((size_t)n * 4 + 255) & ~(size_t)255;
+  const size_t nb_geo = ((size_t)n * kStride * 4 + 255) & ~(size_t)255;
+  char *blk = (char *)c->scratch_alloc(nb_idx + nb_geo + nb_idx, 0);
+  if (!blk) return c->fail(AD_E_OOM, "cannot allocate staging");
+  int *d_idx = (int *)blk;
+  float *d_geo = (float *)(blk + nb_idx);
+  float *d_e = (float *)(blk + nb_idx + nb_geo);
+  HIP_TRY(c, hipMemcpyAsync(d_idx, lig_idx, (size_t)n * 4, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(d_geo, genotypes, (size_t)n * kStride * 4, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, launch_local_search(C, b->cap, n, d_idx, d_geo, d_e, iters, p->rho, p->eps, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(genotypes, d_geo, (size_t)n * kStride * 4, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(energy, d_e, (size_t)n * 4, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return AD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// map-builder argument block (force field in double)
+// ---------------------------------------------------------------------------
+namespace ad {
+size_t map_build_args_size() { return sizeof(MapBuildArgs); }
+
+void fill_map_build_args(void *out, const ad_forcefield &ff, const ad_grid_desc *g, int n_rec, const float *xyz,
+                         const int *type, const float *q, float *out4, float *soa) {
+  MapBuildArgs &A = *reinterpret_cast<MapBuildArgs *>(out);
+  memset(&A, 0, sizeof(A));
+  A.rec_xyz = xyz;
+  A.rec_type = type;
+  A.rec_q = q;
+  A.n_rec = n_rec;
+  A.nx = g->nx;
+  A.ny = g->ny;
+  A.nz = g->nz;
+  A.n_maps = g->n_maps;
+  A.ox = g->origin[0];
+  A.oy = g->origin[1];
+  A.oz = g->origin[2];
+  A.h = g->spacing;
+  for (int m = 0; m < g->n_maps; ++m) A.map_type[m] = g->map_types[m];
+  for (int i = 0; i < ff.n_types; ++i)
+    for (int j = 0; j < ff.n_types; ++j) {
+      int acc = -1;
+      if (ff.hbrole[i] == 1 && ff.hbrole[j] == 2) acc = j;
+      if (ff.hbrole[i] == 2 && ff.hbrole[j] == 1) acc = i;
+      if (acc >= 0) {
+        double R = ff.Rhb[acc], e = ff.epshb[acc], R10 = std::pow(R, 10.0);
+        A.A[i][j] = ff.w_hb * 5.0 * e * R10 * R * R;
+        A.B[i][j] = ff.w_hb * 6.0 * e * R10;
+        A.r0[i][j] = R;
+        A.hb[i][j] = 1;
+      } else {
+        double R = 0.5 * (ff.Rii[i] + ff.Rii[j]), e = std::sqrt(ff.epsii[i] * ff.epsii[j]);
+        double R6 = std::pow(R, 6.0);
+        A.A[i][j] = ff.w_vdw * e * R6 * R6;
+        A.B[i][j] = ff.w_vdw * 2.0 * e * R6;
+        A.r0[i][j] = R;
+        A.hb[i][j] = 0;
+      }
+    }
+  for (int t = 0; t < ff.n_types; ++t) {
+    A.solpar[t] = ff.solpar[t];
+    A.vol[t] = ff.vol[t];
+  }
+  A.w_el_ke = ff.w_el * ff.coulomb;
+  A.w_sol = ff.w_sol;
+  A.qasp = ff.qasp;
+  A.diel_A = ff.diel_A;
+  A.diel_B = ff.diel_eps0 - ff.diel_A;
+  A.diel_k = ff.diel_k;
+  A.diel_lB = ff.diel_lambda * A.diel_B;
+  A.two_s2 = 2.0 * ff.sigma * ff.sigma;
+  A.half_smooth = 0.5 * ff.smooth;
+  A.cutoff2 = ff.cutoff * ff.cutoff;
+  A.cap = ff.cap;
+  A.r_floor = ff.r_floor;
+  A.out4 = out4;
+  A.soa = soa;
+}
+}  // namespace ad
+
+// Docking entry points are implemented in dock.cpp.

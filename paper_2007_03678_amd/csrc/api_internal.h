@@ -1,0 +1,99 @@
+// Context / batch objects of the C ABI and the kernel launch interface.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "ad_internal.h"
+
+namespace ad {
+
+struct EvalConst {
+  FFConst ff;
+  GridArgs grid;
+  BatchArgs batch;
+};
+
+// Arguments of the map-building kernel (passed through device memory).
+struct MapBuildArgs {
+  const float *rec_xyz;
+  const int *rec_type;
+  const float *rec_q;
+  int n_rec;
+  int nx, ny, nz, n_maps;
+  double ox, oy, oz, h;
+  int map_type[kMaxTypes];
+  double A[kMaxTypes][kMaxTypes], B[kMaxTypes][kMaxTypes], r0[kMaxTypes][kMaxTypes];
+  int hb[kMaxTypes][kMaxTypes];
+  double solpar[kMaxTypes], vol[kMaxTypes];
+  double w_el_ke, w_sol, qasp, diel_A, diel_B, diel_k, diel_lB, two_s2, half_smooth, cutoff2, cap, r_floor;
+  float *out4;   // [n_maps][nz][ny][nx] float4 records
+  float *soa;    // [n_maps+2][nz][ny][nx] or null
+};
+
+hipError_t launch_score(const EvalConst &C, int cap, int n, const int *lig_idx, const float *geno, float *E, float *G,
+                        float *T, hipStream_t s);
+hipError_t launch_local_search(const EvalConst &C, int cap, int n, const int *lig_idx, float *geno, float *E,
+                               int iters, double rho, double eps, hipStream_t s);
+hipError_t launch_build_maps(const MapBuildArgs *dev_args, size_t nn, hipStream_t s);
+hipError_t launch_relayout(const float *soa, float *out4, size_t nn, int n_maps, hipStream_t s);
+
+}  // namespace ad
+
+struct ad_batch {
+  ad_ctx *ctx = nullptr;
+  int device = 0;
+  int n_lig = 0;
+  int cap = 64;   // atom capacity of the kernels that serve this batch (64 or 128)
+  ad::LigDesc *lig = nullptr;
+  ad::AtomGeo *geo = nullptr;
+  ad::AtomInfo *info = nullptr;
+  ad::PairRec *pairs = nullptr;
+  ad::TorRec *tors = nullptr;
+  std::vector<ad::LigDesc> lig_host;
+  int map_of_type[AD_MAX_TYPES];   // map index of each type used by the batch at load time (-1: unused)
+};
+
+struct ad_ctx {
+  static constexpr int kScratchSlots = 4;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  ad_forcefield ff;
+  ad::FFConst ffc;
+  std::vector<ad::LJRec> lj_host;
+  ad::LJRec *lj_dev = nullptr;
+  // resident grid
+  bool has_grid = false;
+  int grid_n[3] = {0, 0, 0};
+  double spacing = 0, origin[3] = {0, 0, 0};
+  int n_maps = 0;
+  int map_types[AD_MAX_TYPES];
+  int type_to_map[AD_MAX_TYPES];
+  float *maps4 = nullptr;
+  size_t maps4_bytes = 0;
+  // grow-only scratch buffers
+  void *scratch[kScratchSlots] = {nullptr, nullptr, nullptr, nullptr};
+  size_t scratch_bytes[kScratchSlots] = {0, 0, 0, 0};
+  // docking state buffers
+  void *dock_buf = nullptr;
+  size_t dock_bytes = 0;
+  std::string err;
+
+  int fail(int code, const std::string &msg);
+  int hip_fail(hipError_t e, const char *where);
+  void *scratch_alloc(size_t bytes, int slot);
+  ad::EvalConst eval_const(const ad_batch *b) const;
+  void free_dock_buffers() {
+    if (dock_buf) hipFree(dock_buf);
+    dock_buf = nullptr;
+    dock_bytes = 0;
+  }
+};
+
+namespace ad {
+void fill_map_build_args(void *out, const ad_forcefield &ff, const ad_grid_desc *g, int n_rec, const float *xyz,
+                         const int *type, const float *q, float *out4, float *soa);
+size_t map_build_args_size();
+}  // namespace ad

@@ -1,0 +1,656 @@
+// HIP kernels for gfx950: fused pose + energy + gradient evaluation, local
+// search, GA generations, grid-map construction and grid re-layout.
+//
+// Execution model: one 64-lane wavefront (one work-group) per individual.
+// Lanes map to atoms (atom i on lane i % 64, up to two per lane), to
+// torsions (lane k < 32) and to intramolecular pairs (strided).  Posed
+// coordinates and per-atom force accumulators live in LDS; pair records,
+// torsion records and the grid maps are read through L1/L2.
+//
+// Precision: geometry (pose, distances, grid coordinates and trilinear
+// weights), the energy accumulation and the gradient back-projection run in
+// FP64 -- on CDNA the FP64 FMA rate equals the non-packed FP32 rate, and the
+// energy of a clashing pose is steep enough that FP32 coordinates would move
+// it by more than 1e-5 relative.  The pair potentials themselves
+// (transcendental heavy) run in FP32 with the hardware rsq / rcp / exp2.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "api_internal.h"
+
+namespace ad {
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+__device__ __forceinline__ double wave_incl_scan(double v, int lane) {
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    double o = __shfl_up(v, off);
+    if (lane >= off) v += o;
+  }
+  return v;
+}
+
+__device__ __forceinline__ float fast_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11) and the stream layout of the search:
+// key = (seed lo, seed hi), counter = (ligand id, run, generation,
+// individual << 16 | stream << 10 | word >> 2), word = lane word & 3.
+// ---------------------------------------------------------------------------
+enum : uint32_t { kStInit = 0, kStSelect = 1, kStCross = 2, kStMutate = 3, kStLsPick = 4 };
+
+__device__ __forceinline__ uint4 philox(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+    uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+    c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return c;
+}
+
+struct Rng {
+  uint32_t k0, k1, lig, run, gen;
+  __device__ uint32_t word(uint32_t indiv, uint32_t stream, uint32_t w) const {
+    uint4 o = philox(make_uint4(lig, run, gen, (indiv << 16) | (stream << 10) | (w >> 2)), k0, k1);
+    uint32_t s = w & 3;
+    return s == 0 ? o.x : (s == 1 ? o.y : (s == 2 ? o.z : o.w));
+  }
+  __device__ uint4 block(uint32_t indiv, uint32_t stream, uint32_t blk) const {
+    return philox(make_uint4(lig, run, gen, (indiv << 16) | (stream << 10) | blk), k0, k1);
+  }
+};
+__device__ __forceinline__ double unif(uint32_t x) { return (double)(x >> 8) * (1.0 / 16777216.0); }
+__device__ __forceinline__ uint32_t randint(uint32_t x, uint32_t n) {
+  return (uint32_t)(((uint64_t)x * n) >> 32);
+}
+
+// ---------------------------------------------------------------------------
+// Quaternion helpers (w, x, y, z), FP64.
+// ---------------------------------------------------------------------------
+struct Q4 {
+  double w, x, y, z;
+};
+__device__ __forceinline__ Q4 qmul(Q4 a, Q4 b) {
+  return {a.w * b.w - a.x * b.x - a.y * b.y - a.z * b.z, a.w * b.x + a.x * b.w + a.y * b.z - a.z * b.y,
+          a.w * b.y - a.x * b.z + a.y * b.w + a.z * b.x, a.w * b.z + a.x * b.y - a.y * b.x + a.z * b.w};
+}
+__device__ __forceinline__ Q4 qnormalize(Q4 q) {
+  double n = sqrt(q.w * q.w + q.x * q.x + q.y * q.y + q.z * q.z);
+  double in = 1.0 / n;
+  return {q.w * in, q.x * in, q.y * in, q.z * in};
+}
+// q <- exp(w/2) (x) q, renormalised
+__device__ __forceinline__ Q4 apply_rotvec(Q4 q, double wx, double wy, double wz) {
+  double th = sqrt(wx * wx + wy * wy + wz * wz);
+  double s, c;
+  sincos(0.5 * th, &s, &c);
+  double f = th > 1e-300 ? s / th : 0.5;
+  Q4 r = {c, f * wx, f * wy, f * wz};
+  return qnormalize(qmul(r, q));
+}
+__device__ __forceinline__ double wrap_angle(double th) {
+  const double twopi = 6.283185307179586476925;
+  return th - twopi * floor((th + 3.14159265358979323846) / twopi);
+}
+
+// ---------------------------------------------------------------------------
+// Shared memory of one evaluating wavefront.  CAP = atom capacity (64/128).
+// ---------------------------------------------------------------------------
+template <int CAP>
+struct EvalLds {
+  double x[CAP][3];   // posed coordinates
+  double g[CAP][3];   // dE/dx accumulators
+  union {
+    double tm[kMaxTor][12];   // composite rigid transforms of the fragments (pose phase)
+    double pre[CAP][6];       // inclusive prefix sums of (g, (x-t) x g) (gradient phase)
+  };
+  double geno[kStride];        // genotype being evaluated
+  double grad[kStride];        // output gradient
+};
+
+// Per-lane ligand data that stays in registers across evaluations.
+template <int CAP>
+struct LaneLig {
+  static constexpr int APL = CAP / 64;
+  LigDesc L;
+  double y[APL][3];
+  float q[APL];
+  int map[APL];
+  int owner[APL];
+  // torsion lane data (lane < n_tor)
+  double to[3], tu[3], tinv_len;
+  int tparent, ts, te, ta, tb, tdepth;
+
+  __device__ void load(const EvalConst &C, int li, int lane) {
+    L = C.batch.lig[li];
+#pragma unroll
+    for (int c = 0; c < APL; ++c) {
+      int i = c * 64 + lane;
+      if (i < L.n_atoms) {
+        const AtomGeo &gq = C.batch.geo[L.atom_off + i];
+        const AtomInfo &in = C.batch.info[L.atom_off + i];
+        y[c][0] = gq.y[0];
+        y[c][1] = gq.y[1];
+        y[c][2] = gq.y[2];
+        q[c] = in.q;
+        map[c] = in.map;
+        owner[c] = in.owner;
+      } else {
+        y[c][0] = y[c][1] = y[c][2] = 0;
+        q[c] = 0;
+        map[c] = 0;
+        owner[c] = -1;
+      }
+    }
+    if (lane < L.n_tor) {
+      const TorRec &t = C.batch.tors[L.tor_off + lane];
+      to[0] = t.o[0]; to[1] = t.o[1]; to[2] = t.o[2];
+      tu[0] = t.u[0]; tu[1] = t.u[1]; tu[2] = t.u[2];
+      tinv_len = t.inv_len;
+      tparent = t.parent; ts = t.s; te = t.e; ta = t.a; tb = t.b; tdepth = t.depth;
+    } else {
+      to[0] = to[1] = to[2] = tu[0] = tu[1] = tu[2] = tinv_len = 0;
+      tparent = -1; ts = te = ta = tb = 0; tdepth = 0;
+    }
+  }
+};
+
+// Trilinear interpolation of map_m + q map_e + |q| map_d with its gradient,
+// plus the out-of-box restraint.  FP64.
+__device__ __forceinline__ double grid_energy(const GridArgs &G, double k_out, int m, float qf, const double x[3],
+                                              double g[3]) {
+  const double q = qf, aq = fabs(q);
+  const double u[3] = {(x[0] - G.ox) * G.inv_h, (x[1] - G.oy) * G.inv_h, (x[2] - G.oz) * G.inv_h};
+  const int n[3] = {G.nx, G.ny, G.nz};
+  double f[3], uc[3];
+  int i0[3];
+  bool clamped[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    double top = (double)(n[d] - 1);
+    clamped[d] = !(u[d] >= 0.0 && u[d] <= top);    // NaN counts as clamped
+    uc[d] = fmin(fmax(u[d], 0.0), top);             // NaN -> 0 (fmax drops NaN)
+    int ii = (int)floor(uc[d]);
+    ii = min(max(ii, 0), n[d] - 2);
+    i0[d] = ii;
+    f[d] = uc[d] - (double)ii;
+  }
+  const float4 *M = reinterpret_cast<const float4 *>(G.maps);
+  const size_t sx = 1, sy = (size_t)G.nx, sz = (size_t)G.nx * G.ny;
+  const size_t base = (size_t)m * sz * G.nz + (size_t)i0[2] * sz + (size_t)i0[1] * sy + (size_t)i0[0];
+  double v[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    size_t off = base + ((c & 1) ? sx : 0) + ((c & 2) ? sy : 0) + ((c & 4) ? sz : 0);
+    const float4 r = M[off];
+    v[c] = (double)r.x + q * (double)r.y + aq * (double)r.z;
+  }
+  const double fx = f[0], fy = f[1], fz = f[2];
+  const double gx = 1.0 - fx, gy = 1.0 - fy, gz = 1.0 - fz;
+  // along x
+  double a00 = v[0] * gx + v[1] * fx, a10 = v[2] * gx + v[3] * fx;
+  double a01 = v[4] * gx + v[5] * fx, a11 = v[6] * gx + v[7] * fx;
+  double b0 = a00 * gy + a10 * fy, b1 = a01 * gy + a11 * fy;
+  double E = b0 * gz + b1 * fz;
+  double dx00 = v[1] - v[0], dx10 = v[3] - v[2], dx01 = v[5] - v[4], dx11 = v[7] - v[6];
+  double dEdu0 = ((dx00 * gy + dx10 * fy) * gz + (dx01 * gy + dx11 * fy) * fz);
+  double dEdu1 = ((a10 - a00) * gz + (a11 - a01) * fz);
+  double dEdu2 = (b1 - b0);
+  double dEdu[3] = {dEdu0, dEdu1, dEdu2};
+  const double o[3] = {G.ox, G.oy, G.oz};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if (!clamped[d]) {
+      g[d] = dEdu[d] * G.inv_h;
+    } else {
+      double dd = x[d] - (o[d] + G.h * uc[d]);
+      E += k_out * dd * dd;
+      g[d] = 2.0 * k_out * dd;
+    }
+  }
+  return E;
+}
+
+// One intramolecular pair in FP32: returns the energy, writes dE/dr / r.
+__device__ __forceinline__ float pair_energy(const FFConst &K, const LJRec lj, float qq, float dsv, float r2,
+                                             float *fscale) {
+  const bool floored = !(r2 >= K.r_floor2);
+  const float r2c = floored ? K.r_floor2 : r2;
+  const float inv_r = fast_rsq(r2c);
+  const float r = r2c * inv_r;
+  // smoothed 12-6 / 12-10
+  const float dr = r - lj.r0;
+  const float sh = fminf(fmaxf(dr, -K.half_smooth), K.half_smooth);
+  const float rr = r - sh;
+  const float slope = fabsf(dr) > K.half_smooth ? 1.0f : 0.0f;
+  const float inv = fast_rcp(rr);
+  const float i2 = inv * inv, i6 = i2 * i2 * i2, i12 = i6 * i6;
+  const bool hb = lj.hb != 0.0f;
+  const float im = hb ? i6 * i2 * i2 : i6;
+  const float mm = hb ? 10.0f : 6.0f;
+  const float e_lj = lj.A * i12 - lj.B * im;
+  const float d_lj = slope * (mm * lj.B * im - 12.0f * lj.A * i12) * inv;
+  // distance-dependent dielectric electrostatics: qq D / (N r), D = 1 + k e, N = A D + B
+  const float ex = fast_exp2(-K.diel_lB_log2e * r);
+  const float D = 1.0f + K.diel_k * ex;
+  const float N = K.diel_A * D + K.diel_B;
+  const float inv_Nr = fast_rcp(N * r);
+  const float e_el = qq * D * inv_Nr;
+  const float d_el = -qq * (D * N + K.diel_c1 * r * ex) * inv_Nr * inv_Nr;
+  // desolvation
+  const float gds = fast_exp2(-K.ds_log2e * r2c);
+  const float e_ds = dsv * gds;
+  const float d_ds = -e_ds * r * K.inv_s2;
+  *fscale = floored ? 0.0f : (d_lj + d_el + d_ds) * inv_r;
+  return e_lj + e_el + e_ds;
+}
+
+// Rodrigues rotation matrix of angle th about unit u (row major 3x3).
+__device__ __forceinline__ void rot_matrix(const double u[3], double c, double s, double R[9]) {
+  const double t = 1.0 - c;
+  R[0] = c + t * u[0] * u[0];
+  R[1] = t * u[0] * u[1] - s * u[2];
+  R[2] = t * u[0] * u[2] + s * u[1];
+  R[3] = t * u[1] * u[0] + s * u[2];
+  R[4] = c + t * u[1] * u[1];
+  R[5] = t * u[1] * u[2] - s * u[0];
+  R[6] = t * u[2] * u[0] - s * u[1];
+  R[7] = t * u[2] * u[1] + s * u[0];
+  R[8] = c + t * u[2] * u[2];
+}
+
+// Evaluate the genotype in S.geno.  Returns the total energy (every lane);
+// with GRAD the gradient is written to S.grad[0..39]; terms (lane 0) gets
+// {inter, intra}.  Ends with the LDS in a consistent state (barrier).
+template <int CAP, bool GRAD>
+__device__ double evaluate(const EvalConst &C, const LaneLig<CAP> &LL, EvalLds<CAP> &S, int lane, double *inter_out,
+                           double *intra_out) {
+  constexpr int APL = CAP / 64;
+  const LigDesc &L = LL.L;
+  // global rigid transform: x = R (y) + t, y relative to the centre
+  const double t0 = S.geno[0], t1 = S.geno[1], t2 = S.geno[2];
+  Q4 q = qnormalize({S.geno[3], S.geno[4], S.geno[5], S.geno[6]});
+  double R[9] = {1 - 2 * (q.y * q.y + q.z * q.z), 2 * (q.x * q.y - q.w * q.z), 2 * (q.x * q.z + q.w * q.y),
+                 2 * (q.x * q.y + q.w * q.z), 1 - 2 * (q.x * q.x + q.z * q.z), 2 * (q.y * q.z - q.w * q.x),
+                 2 * (q.x * q.z - q.w * q.y), 2 * (q.y * q.z + q.w * q.x), 1 - 2 * (q.x * q.x + q.y * q.y)};
+  // torsion transforms T_k(y) = Rk (y - o) + o, composed root-ward level by
+  // level: C_k = C_parent o T_k with C_root = global transform
+  double Rk[9], wk[3];
+  if (lane < L.n_tor) {
+    double s, c;
+    sincos(S.geno[7 + lane], &s, &c);
+    rot_matrix(LL.tu, c, s, Rk);
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+      wk[r] = LL.to[r] - (Rk[3 * r] * LL.to[0] + Rk[3 * r + 1] * LL.to[1] + Rk[3 * r + 2] * LL.to[2]);
+  }
+  for (int level = 1; level <= L.max_depth; ++level) {
+    if (lane < L.n_tor && LL.tdepth == level) {
+      double M[12];
+      if (LL.tparent < 0) {
+#pragma unroll
+        for (int e = 0; e < 9; ++e) M[e] = R[e];
+        M[9] = t0; M[10] = t1; M[11] = t2;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 12; ++e) M[e] = S.tm[LL.tparent][e];
+      }
+      double out[12];
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc)
+          out[3 * r + cc] = M[3 * r] * Rk[cc] + M[3 * r + 1] * Rk[3 + cc] + M[3 * r + 2] * Rk[6 + cc];
+        out[9 + r] = M[3 * r] * wk[0] + M[3 * r + 1] * wk[1] + M[3 * r + 2] * wk[2] + M[9 + r];
+      }
+#pragma unroll
+      for (int e = 0; e < 12; ++e) S.tm[lane][e] = out[e];
+    }
+    __syncthreads();
+  }
+  // atoms: pose and inter-molecular energy
+  double e_inter = 0.0;
+#pragma unroll
+  for (int c = 0; c < APL; ++c) {
+    const int i = c * 64 + lane;
+    if (i < L.n_atoms) {
+      const double *yy = LL.y[c];
+      double x[3];
+      if (LL.owner[c] < 0) {
+#pragma unroll
+        for (int r = 0; r < 3; ++r) x[r] = R[3 * r] * yy[0] + R[3 * r + 1] * yy[1] + R[3 * r + 2] * yy[2];
+        x[0] += t0; x[1] += t1; x[2] += t2;
+      } else {
+        const double *M = S.tm[LL.owner[c]];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) x[r] = M[3 * r] * yy[0] + M[3 * r + 1] * yy[1] + M[3 * r + 2] * yy[2] + M[9 + r];
+      }
+      double g[3];
+      e_inter += grid_energy(C.grid, C.ff.k_out, LL.map[c], LL.q[c], x, g);
+      S.x[i][0] = x[0]; S.x[i][1] = x[1]; S.x[i][2] = x[2];
+      if (GRAD) { S.g[i][0] = g[0]; S.g[i][1] = g[1]; S.g[i][2] = g[2]; }
+    }
+  }
+  __syncthreads();
+  // intramolecular pairs
+  double e_intra = 0.0;
+  const PairRec *pr = C.batch.pairs + L.pair_off;
+  const LJRec *ljt = C.batch.lj;
+  for (int p = lane; p < L.n_pairs; p += 64) {
+    const PairRec rec = pr[p];
+    const int i = rec.ijt & 0xff, j = (rec.ijt >> 8) & 0xff, tp = rec.ijt >> 16;
+    const double dx = S.x[i][0] - S.x[j][0], dy = S.x[i][1] - S.x[j][1], dz = S.x[i][2] - S.x[j][2];
+    const float r2 = (float)(dx * dx + dy * dy + dz * dz);
+    float fs;
+    e_intra += (double)pair_energy(C.ff, ljt[tp], rec.qq, rec.dsv, r2, &fs);
+    if (GRAD) {
+      const double f = (double)fs;
+      atomicAdd(&S.g[i][0], f * dx);
+      atomicAdd(&S.g[i][1], f * dy);
+      atomicAdd(&S.g[i][2], f * dz);
+      atomicAdd(&S.g[j][0], -f * dx);
+      atomicAdd(&S.g[j][1], -f * dy);
+      atomicAdd(&S.g[j][2], -f * dz);
+    }
+  }
+  const double inter = wave_sum(e_inter), intra = wave_sum(e_intra);
+  if (inter_out) *inter_out = inter;
+  if (intra_out) *intra_out = intra;
+  if (!GRAD) return inter + intra;
+  __syncthreads();
+  // gradient back-projection: prefix sums over the internal atom order of
+  // v_i = (g_i, (x_i - t) x g_i); each torsion's moving set is a range
+  double carry[6] = {0, 0, 0, 0, 0, 0};
+  double vv[APL][6];
+#pragma unroll
+  for (int c = 0; c < APL; ++c) {
+    const int i = c * 64 + lane;
+    if (i < L.n_atoms) {
+      const double gx = S.g[i][0], gy = S.g[i][1], gz = S.g[i][2];
+      const double rx = S.x[i][0] - t0, ry = S.x[i][1] - t1, rz = S.x[i][2] - t2;
+      vv[c][0] = gx; vv[c][1] = gy; vv[c][2] = gz;
+      vv[c][3] = ry * gz - rz * gy;
+      vv[c][4] = rz * gx - rx * gz;
+      vv[c][5] = rx * gy - ry * gx;
+    } else {
+#pragma unroll
+      for (int e = 0; e < 6; ++e) vv[c][e] = 0.0;
+    }
+  }
+  __syncthreads();   // tm (pose phase) is dead; pre aliases it
+#pragma unroll
+  for (int c = 0; c < APL; ++c) {
+    const int i = c * 64 + lane;
+#pragma unroll
+    for (int e = 0; e < 6; ++e) {
+      double s = wave_incl_scan(vv[c][e], lane) + carry[e];
+      if (i < L.n_atoms) S.pre[i][e] = s;
+      carry[e] = __shfl(s, 63);
+    }
+  }
+  __syncthreads();
+  const int nl = L.n_atoms - 1;
+  if (lane < kStride) {
+    double gv = 0.0;
+    if (lane < 6) gv = S.pre[nl][lane];   // dE/dt and dE/domega: totals
+    S.grad[lane] = gv;
+  }
+  if (lane < L.n_tor) {
+    double F[6];
+#pragma unroll
+    for (int e = 0; e < 6; ++e) F[e] = S.pre[LL.te - 1][e] - (LL.ts > 0 ? S.pre[LL.ts - 1][e] : 0.0);
+    const double ax = S.x[LL.ta][0] - t0, ay = S.x[LL.ta][1] - t1, az = S.x[LL.ta][2] - t2;
+    // torque about the axis point a: sum (x_i - t) x g_i - (x_a - t) x sum g_i
+    const double tx = F[3] - (ay * F[2] - az * F[1]);
+    const double ty = F[4] - (az * F[0] - ax * F[2]);
+    const double tz = F[5] - (ax * F[1] - ay * F[0]);
+    const double ux = (S.x[LL.tb][0] - S.x[LL.ta][0]) * LL.tinv_len;
+    const double uy = (S.x[LL.tb][1] - S.x[LL.ta][1]) * LL.tinv_len;
+    const double uz = (S.x[LL.tb][2] - S.x[LL.ta][2]) * LL.tinv_len;
+    S.grad[7 + lane] = ux * tx + uy * ty + uz * tz;
+  }
+  __syncthreads();
+  return inter + intra;
+}
+
+__device__ __forceinline__ bool genotype_finite(const double *geno, int n_tor) {
+  bool ok = true;
+  for (int e = 0; e < 7 + n_tor; ++e) ok = ok && isfinite(geno[e]);
+  return ok;
+}
+
+// ---------------------------------------------------------------------------
+// ad_score_poses: one work-group (one wavefront) per pose.
+// ---------------------------------------------------------------------------
+template <int CAP, bool GRAD>
+__global__ __launch_bounds__(64) void k_score(EvalConst C, int n, const int *__restrict__ lig_idx,
+                                              const float *__restrict__ geno, float *__restrict__ E_out,
+                                              float *__restrict__ G_out, float *__restrict__ T_out) {
+  __shared__ EvalLds<CAP> S;
+  const int p = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int li = lig_idx[p];
+  if (li < 0 || li >= C.batch.n_lig || C.batch.lig[li].n_atoms > CAP) {
+    // invalid index (only reachable with device-side indices): NaN result
+    if (lane == 0) E_out[(size_t)p] = __builtin_nanf("");
+    if (GRAD && G_out && lane < kStride) G_out[(size_t)p * kStride + lane] = __builtin_nanf("");
+    if (T_out && lane < 3) T_out[(size_t)p * 3 + lane] = __builtin_nanf("");
+    return;
+  }
+  LaneLig<CAP> LL;
+  LL.load(C, li, lane);
+  if (lane < kStride) S.geno[lane] = (double)geno[(size_t)p * kStride + lane];
+  __syncthreads();
+  double inter, intra;
+  double E = evaluate<CAP, GRAD>(C, LL, S, lane, &inter, &intra);
+  const bool fin = genotype_finite(S.geno, LL.L.n_tor);
+  const float nanf = __builtin_nanf("");
+  if (lane == 0) E_out[p] = fin ? (float)E : nanf;
+  if (T_out && lane < 3) {
+    double tv = lane == 0 ? inter : (lane == 1 ? intra : inter + (double)C.ff.w_tor * LL.L.n_tor);
+    T_out[(size_t)p * 3 + lane] = fin ? (float)tv : nanf;
+  }
+  if (GRAD && lane < kStride) {
+    double gv = (lane == 6 || lane >= 7 + LL.L.n_tor) ? 0.0 : S.grad[lane];
+    G_out[(size_t)p * kStride + lane] = fin ? (float)gv : nanf;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// ADADELTA local search: one wavefront per individual, `iters` evaluations.
+// Degrees of freedom on lanes: 0-2 translation, 3-5 rotation vector,
+// 7..7+T-1 torsions (lane 6 is the fourth quaternion slot).
+// ---------------------------------------------------------------------------
+template <int CAP>
+__device__ void adadelta_wave(const EvalConst &C, const LaneLig<CAP> &LL, EvalLds<CAP> &S, int lane, float *geno_io,
+                              float *E_io, int iters, double rho, double eps) {
+  const int T = LL.L.n_tor;
+  double gene = lane < kStride ? (double)geno_io[lane] : 0.0;
+  double best_gene = gene, best_E = INFINITY;
+  double Eg2 = 0.0, Edx2 = 0.0;
+  const bool dof = lane < 6 || (lane >= 7 && lane < 7 + T);
+  for (int it = 0; it < iters; ++it) {
+    if (lane < kStride) S.geno[lane] = gene;
+    __syncthreads();
+    const double E = evaluate<CAP, true>(C, LL, S, lane, nullptr, nullptr);
+    const double gd = dof ? S.grad[lane] : 0.0;
+    if (E < best_E) {
+      best_E = E;
+      best_gene = gene;
+    }
+    Eg2 = rho * Eg2 + (1.0 - rho) * gd * gd;
+    const double dx = dof ? -sqrt(Edx2 + eps) / sqrt(Eg2 + eps) * gd : 0.0;
+    Edx2 = rho * Edx2 + (1.0 - rho) * dx * dx;
+    // orientation: q <- exp(dw/2) (x) q using the three rotation lanes
+    const double w0 = __shfl(dx, 3), w1 = __shfl(dx, 4), w2 = __shfl(dx, 5);
+    Q4 qc = {__shfl(gene, 3), __shfl(gene, 4), __shfl(gene, 5), __shfl(gene, 6)};
+    Q4 qn = apply_rotvec(qc, w0, w1, w2);
+    if (lane < 3) gene += dx;
+    else if (lane == 3) gene = qn.w;
+    else if (lane == 4) gene = qn.x;
+    else if (lane == 5) gene = qn.y;
+    else if (lane == 6) gene = qn.z;
+    else if (lane < 7 + T) gene = wrap_angle(gene + dx);
+    __syncthreads();
+  }
+  if (lane < kStride) geno_io[lane] = (float)best_gene;
+  if (lane == 0) *E_io = (float)best_E;
+}
+
+template <int CAP>
+__global__ __launch_bounds__(64) void k_local_search(EvalConst C, int n, const int *__restrict__ lig_idx,
+                                                     float *__restrict__ geno, float *__restrict__ E, int iters,
+                                                     double rho, double eps) {
+  __shared__ EvalLds<CAP> S;
+  const int p = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int li = lig_idx[p];
+  if (li < 0 || li >= C.batch.n_lig || C.batch.lig[li].n_atoms > CAP) {
+    if (lane == 0) E[p] = __builtin_nanf("");
+    return;
+  }
+  LaneLig<CAP> LL;
+  LL.load(C, li, lane);
+  adadelta_wave<CAP>(C, LL, S, lane, geno + (size_t)p * kStride, E + p, iters, rho, eps);
+}
+
+// ---------------------------------------------------------------------------
+// Grid maps: one thread per node, receptor atoms staged through LDS.  FP64.
+// Writes the float4 resident layout and, optionally, the SoA layout.
+// ---------------------------------------------------------------------------
+constexpr int kMapTile = 256;
+
+__global__ __launch_bounds__(256) void k_build_maps(const MapBuildArgs *__restrict__ Ap) {
+  const MapBuildArgs &A = *Ap;
+  __shared__ double sx[kMapTile], sy[kMapTile], sz[kMapTile], sq[kMapTile];
+  __shared__ int st[kMapTile];
+  const size_t nn = (size_t)A.nx * A.ny * A.nz;
+  const size_t node = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool active = node < nn;
+  const int i = active ? (int)(node % A.nx) : 0;
+  const int j = active ? (int)((node / A.nx) % A.ny) : 0;
+  const int k = active ? (int)(node / ((size_t)A.nx * A.ny)) : 0;
+  const double px = A.ox + A.h * i, py = A.oy + A.h * j, pz = A.oz + A.h * k;
+  double aff[kMaxTypes];
+  for (int m = 0; m < kMaxTypes; ++m) aff[m] = 0.0;
+  double elec = 0.0, desolv = 0.0;
+  for (int base = 0; base < A.n_rec; base += kMapTile) {
+    __syncthreads();
+    const int a = base + threadIdx.x;
+    if (a < A.n_rec) {
+      sx[threadIdx.x] = A.rec_xyz[3 * a];
+      sy[threadIdx.x] = A.rec_xyz[3 * a + 1];
+      sz[threadIdx.x] = A.rec_xyz[3 * a + 2];
+      sq[threadIdx.x] = A.rec_q[a];
+      st[threadIdx.x] = A.rec_type[a];
+    }
+    __syncthreads();
+    const int cnt = min(kMapTile, A.n_rec - base);
+    for (int b = 0; b < cnt; ++b) {
+      const double dx = px - sx[b], dy = py - sy[b], dz = pz - sz[b];
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      const double r = sqrt(r2);
+      const double rf = r < A.r_floor ? A.r_floor : r;
+      const int ta = st[b];
+      const double qa = sq[b];
+      // electrostatics over all atoms
+      const double e = exp(-A.diel_lB * rf);
+      const double den = 1.0 + A.diel_k * e;
+      const double eps = A.diel_A + A.diel_B / den;
+      elec += A.w_el_ke * qa / (eps * rf);
+      if (r2 < A.cutoff2) {
+        const double gds = exp(-rf * rf / A.two_s2);
+        const double Sa = A.solpar[ta] + A.qasp * fabs(qa);
+        desolv += A.w_sol * A.qasp * A.vol[ta] * gds;
+        for (int m = 0; m < A.n_maps; ++m) {
+          const int t = A.map_type[m];
+          const double r0 = A.r0[t][ta];
+          double rr;
+          if (rf > r0 + A.half_smooth) rr = rf - A.half_smooth;
+          else if (rf < r0 - A.half_smooth) rr = rf + A.half_smooth;
+          else rr = r0;
+          const double inv = 1.0 / rr, i2 = inv * inv, i6 = i2 * i2 * i2;
+          const double im = A.hb[t][ta] ? i6 * i2 * i2 : i6;
+          aff[m] += A.A[t][ta] * i6 * i6 - A.B[t][ta] * im + A.w_sol * (A.solpar[t] * A.vol[ta] + Sa * A.vol[t]) * gds;
+        }
+      }
+    }
+  }
+  if (!active) return;
+  for (int m = 0; m < A.n_maps; ++m) {
+    const float v = (float)fmin(aff[m], A.cap);
+    float4 rec = make_float4(v, (float)elec, (float)desolv, 0.0f);
+    reinterpret_cast<float4 *>(A.out4)[(size_t)m * nn + node] = rec;
+    if (A.soa) A.soa[(size_t)m * nn + node] = v;
+  }
+  if (A.soa) {
+    A.soa[(size_t)A.n_maps * nn + node] = (float)elec;
+    A.soa[(size_t)(A.n_maps + 1) * nn + node] = (float)desolv;
+  }
+}
+
+// SoA [n_maps+2][nodes] -> float4 per (map, node).
+__global__ void k_relayout(const float *__restrict__ soa, float *__restrict__ out4, size_t nn, int n_maps) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nn * n_maps) return;
+  const size_t m = idx / nn, node = idx % nn;
+  float4 r = make_float4(soa[m * nn + node], soa[(size_t)n_maps * nn + node], soa[(size_t)(n_maps + 1) * nn + node],
+                         0.0f);
+  reinterpret_cast<float4 *>(out4)[idx] = r;
+}
+
+// ---------------------------------------------------------------------------
+// launch wrappers (called by the C-ABI layer)
+// ---------------------------------------------------------------------------
+hipError_t launch_score(const EvalConst &C, int cap, int n, const int *lig_idx, const float *geno, float *E, float *G,
+                        float *T, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  dim3 grid(n), block(64);
+  if (cap <= 64) {
+    if (G) hipLaunchKernelGGL((k_score<64, true>), grid, block, 0, s, C, n, lig_idx, geno, E, G, T);
+    else hipLaunchKernelGGL((k_score<64, false>), grid, block, 0, s, C, n, lig_idx, geno, E, G, T);
+  } else {
+    if (G) hipLaunchKernelGGL((k_score<128, true>), grid, block, 0, s, C, n, lig_idx, geno, E, G, T);
+    else hipLaunchKernelGGL((k_score<128, false>), grid, block, 0, s, C, n, lig_idx, geno, E, G, T);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_local_search(const EvalConst &C, int cap, int n, const int *lig_idx, float *geno, float *E,
+                               int iters, double rho, double eps, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  dim3 grid(n), block(64);
+  if (cap <= 64) hipLaunchKernelGGL((k_local_search<64>), grid, block, 0, s, C, n, lig_idx, geno, E, iters, rho, eps);
+  else hipLaunchKernelGGL((k_local_search<128>), grid, block, 0, s, C, n, lig_idx, geno, E, iters, rho, eps);
+  return hipGetLastError();
+}
+
+hipError_t launch_build_maps(const MapBuildArgs *dev_args, size_t nn, hipStream_t s) {
+  dim3 grid((unsigned)((nn + 255) / 256)), block(256);
+  hipLaunchKernelGGL(k_build_maps, grid, block, 0, s, dev_args);
+  return hipGetLastError();
+}
+
+hipError_t launch_relayout(const float *soa, float *out4, size_t nn, int n_maps, hipStream_t s) {
+  size_t total = nn * n_maps;
+  dim3 grid((unsigned)((total + 255) / 256)), block(256);
+  hipLaunchKernelGGL(k_relayout, grid, block, 0, s, soa, out4, nn, n_maps);
+  return hipGetLastError();
+}
+
+
+}  // namespace ad
