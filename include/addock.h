@@ -148,8 +148,11 @@ int ad_ligand_check(const ad_ligand *lig, int n_types, char *msg, int msg_len);
  * valid across grid reloads that keep the map types. */
 int ad_load_ligands(ad_ctx *ctx, int n, const ad_ligand *ligs, ad_batch **out);
 void ad_free_batch(ad_batch *b);
-/* Per-ligand sizes: atoms, torsions, intramolecular pairs, rigid fragments. */
-int ad_batch_info(const ad_batch *b, int lig, int *n_atoms, int *n_torsions, int *n_pairs, int *n_fragments);
+/* Per-ligand sizes: atoms, torsions, intramolecular pairs, rigid fragments,
+ * and depth_sum = sum over atoms of the number of torsions that move the
+ * atom (each output pointer may be NULL). */
+int ad_batch_info(const ad_batch *b, int lig, int *n_atoms, int *n_torsions, int *n_pairs, int *n_fragments,
+                  int *depth_sum);
 
 /* ---- scoring: the hot path ----------------------------------------------
  * ad_score_poses: for pose p, ligand lig_idx[p] of the batch and genotype
@@ -222,6 +225,21 @@ int ad_local_search(ad_ctx *ctx, const ad_batch *b, int n, const int *lig_idx, f
  * (ligand, run), [pop][40] host, exactly as ad_dock_batch draws them. */
 int ad_initial_population(ad_ctx *ctx, const ad_batch *b, int lig, uint32_t lig_id, int run, int pop,
                           uint64_t seed, float *genotypes);
+
+/* ---- diagnostics ----------------------------------------------------------
+ * Kernel timing with HIP events recorded on the context's stream around
+ * every launch of the docking and scoring kernels, for throughput and
+ * roofline reporting.  Kinds: 0 initial population, 1 GA generation,
+ * 2 local-search generation (and ad_local_search), 3 scoring.  Times are
+ * accumulated when a call completes; ad_get_kernel_timing reads (and with
+ * reset != 0 clears) them.  Timing adds two event records per launch. */
+#define AD_KERNEL_KINDS 4
+typedef struct {
+  double ms[AD_KERNEL_KINDS];
+  int64_t launches[AD_KERNEL_KINDS];
+} ad_kernel_times;
+int ad_set_kernel_timing(ad_ctx *ctx, int enable);
+int ad_get_kernel_timing(ad_ctx *ctx, ad_kernel_times *out, int reset);
 
 #ifdef __cplusplus
 }

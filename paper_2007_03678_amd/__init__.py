@@ -25,7 +25,8 @@ MAX_TYPES, STRIDE = 16, 40
 
 EXPORTS = ["ad_create", "ad_destroy", "ad_last_error", "ad_set_stream", "ad_synchronize", "ad_load_grids",
            "ad_build_grids", "ad_ligand_check", "ad_load_ligands", "ad_free_batch", "ad_batch_info",
-           "ad_score_poses", "ad_dock_batch", "ad_local_search", "ad_initial_population"]
+           "ad_score_poses", "ad_dock_batch", "ad_local_search", "ad_initial_population",
+           "ad_set_kernel_timing", "ad_get_kernel_timing"]
 
 
 def build(verbose: bool = False, arch: str = "gfx950") -> str:
@@ -77,6 +78,13 @@ class DockParams(C.Structure):
                 ("ls_method", C.c_int), ("autostop", C.c_int)]
 
 
+class KernelTimes(C.Structure):
+    _fields_ = [("ms", C.c_double * 4), ("launches", C.c_int64 * 4)]
+
+
+KERNEL_KINDS = ("init", "ga", "ls", "score")
+
+
 class DockResult(C.Structure):
     _fields_ = [("best_energy", C.c_float), ("best_score", C.c_float),
                 ("best_genotype", C.c_float * STRIDE), ("best_run", C.c_int),
@@ -117,7 +125,9 @@ def lib():
     L.ad_load_ligands.argtypes = [vp, C.c_int, C.POINTER(Ligand), C.POINTER(vp)]
     L.ad_free_batch.argtypes = [vp]
     L.ad_free_batch.restype = None
-    L.ad_batch_info.argtypes = [vp, C.c_int, ip, ip, ip, ip]
+    L.ad_batch_info.argtypes = [vp, C.c_int, ip, ip, ip, ip, ip]
+    L.ad_set_kernel_timing.argtypes = [vp, C.c_int]
+    L.ad_get_kernel_timing.argtypes = [vp, C.POINTER(KernelTimes), C.c_int]
     L.ad_score_poses.argtypes = [vp, vp, C.c_int, vp, vp, vp, vp, vp, C.c_int]
     L.ad_dock_batch.argtypes = [vp, vp, C.POINTER(DockParams), C.c_uint64, vp, C.POINTER(DockResult), fp, fp]
     L.ad_local_search.argtypes = [vp, vp, C.c_int, vp, vp, vp, C.POINTER(DockParams), C.c_int, C.c_int]
@@ -215,11 +225,12 @@ class Batch:
         self.n = n
 
     def info(self, i):
-        a, t, p, f = C.c_int(), C.c_int(), C.c_int(), C.c_int()
-        rc = lib().ad_batch_info(self.h, i, C.byref(a), C.byref(t), C.byref(p), C.byref(f))
+        a, t, p, f, d = C.c_int(), C.c_int(), C.c_int(), C.c_int(), C.c_int()
+        rc = lib().ad_batch_info(self.h, i, C.byref(a), C.byref(t), C.byref(p), C.byref(f), C.byref(d))
         if rc:
             raise AddockError(rc, "bad ligand index")
-        return dict(n_atoms=a.value, n_torsions=t.value, n_pairs=p.value, n_fragments=f.value)
+        return dict(n_atoms=a.value, n_torsions=t.value, n_pairs=p.value, n_fragments=f.value,
+                    depth_sum=d.value)
 
     def free(self):
         if self.h:
@@ -252,6 +263,14 @@ class Context:
     def _check(self, rc):
         if rc:
             raise AddockError(rc, lib().ad_last_error(self.h).decode())
+
+    def ad_set_kernel_timing(self, enable: bool):
+        self._check(lib().ad_set_kernel_timing(self.h, 1 if enable else 0))
+
+    def ad_get_kernel_timing(self, reset: bool = False):
+        t = KernelTimes()
+        self._check(lib().ad_get_kernel_timing(self.h, C.byref(t), 1 if reset else 0))
+        return {k: (t.ms[i], int(t.launches[i])) for i, k in enumerate(KERNEL_KINDS)}
 
     def ad_synchronize(self):
         self._check(lib().ad_synchronize(self.h))

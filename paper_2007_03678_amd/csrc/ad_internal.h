@@ -101,7 +101,7 @@ struct BatchArgs {
 
 // Host-side prepared ligand (before upload).
 struct PreparedLigand {
-  int n_atoms = 0, n_tor = 0, n_frag = 0, max_depth = 0;
+  int n_atoms = 0, n_tor = 0, n_frag = 0, max_depth = 0, depth_sum = 0;
   std::vector<AtomGeo> geo;
   std::vector<AtomInfo> info;
   std::vector<PairRec> pairs;

@@ -156,6 +156,7 @@ extern "C" void ad_destroy(ad_ctx *c) {
   if (!c) return;
   hipSetDevice(c->device);
   if (c->stream) hipStreamSynchronize(c->stream);
+  for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
   if (c->maps4) hipFree(c->maps4);
   if (c->lj_dev) hipFree(c->lj_dev);
   for (int s = 0; s < ad_ctx::kScratchSlots; ++s)
@@ -364,6 +365,8 @@ extern "C" int ad_load_ligands(ad_ctx *c, int n, const ad_ligand *ligs, ad_batch
   }
   b->cap = cap;
   b->lig_host = lig;
+  b->depth_sum.resize(n);
+  for (int i = 0; i < n; ++i) b->depth_sum[i] = prep[i].depth_sum;
   for (int t = 0; t < AD_MAX_TYPES; ++t) b->map_of_type[t] = -1;
   for (int i = 0; i < n; ++i)
     for (int a = 0; a < ligs[i].n_atoms; ++a) b->map_of_type[ligs[i].type_id[a]] = c->type_to_map[ligs[i].type_id[a]];
@@ -399,13 +402,14 @@ extern "C" void ad_free_batch(ad_batch *b) {
 }
 
 extern "C" int ad_batch_info(const ad_batch *b, int lig, int *n_atoms, int *n_torsions, int *n_pairs,
-                             int *n_fragments) {
+                             int *n_fragments, int *depth_sum) {
   if (!b || lig < 0 || lig >= b->n_lig) return AD_E_INVALID;
   const LigDesc &d = b->lig_host[lig];
   if (n_atoms) *n_atoms = d.n_atoms;
   if (n_torsions) *n_torsions = d.n_tor;
   if (n_pairs) *n_pairs = d.n_pairs;
   if (n_fragments) *n_fragments = d.n_frag;
+  if (depth_sum) *depth_sum = b->depth_sum[lig];
   return AD_OK;
 }
 
@@ -434,7 +438,9 @@ extern "C" int ad_score_poses(ad_ctx *c, const ad_batch *b, int n, const int *li
   hipSetDevice(c->device);
   const EvalConst C = c->eval_const(b);
   if (ptrs_on_device) {
+    const int t0 = c->timing_begin(3);
     HIP_TRY(c, launch_score(C, b->cap, n, lig_idx, genotypes, energy, grad, terms, c->stream));
+    c->timing_end(3, t0);
     return AD_OK;
   }
   for (int p = 0; p < n; ++p)
@@ -453,11 +459,14 @@ extern "C" int ad_score_poses(ad_ctx *c, const ad_batch *b, int n, const int *li
   float *d_t = terms ? (float *)(blk + nb_idx + nb_geo + nb_e + nb_g) : nullptr;
   HIP_TRY(c, hipMemcpyAsync(d_idx, lig_idx, (size_t)n * 4, hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipMemcpyAsync(d_geo, genotypes, (size_t)n * kStride * 4, hipMemcpyHostToDevice, c->stream));
+  const int t0 = c->timing_begin(3);
   HIP_TRY(c, launch_score(C, b->cap, n, d_idx, d_geo, d_e, d_g, d_t, c->stream));
+  c->timing_end(3, t0);
   HIP_TRY(c, hipMemcpyAsync(energy, d_e, (size_t)n * 4, hipMemcpyDeviceToHost, c->stream));
   if (grad) HIP_TRY(c, hipMemcpyAsync(grad, d_g, (size_t)n * kStride * 4, hipMemcpyDeviceToHost, c->stream));
   if (terms) HIP_TRY(c, hipMemcpyAsync(terms, d_t, (size_t)n * 12, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->timing_collect();
   return AD_OK;
 }
 
@@ -473,7 +482,9 @@ extern "C" int ad_local_search(ad_ctx *c, const ad_batch *b, int n, const int *l
   hipSetDevice(c->device);
   const EvalConst C = c->eval_const(b);
   if (ptrs_on_device) {
+    const int t0 = c->timing_begin(2);
     HIP_TRY(c, launch_local_search(C, b->cap, n, lig_idx, genotypes, energy, iters, p->rho, p->eps, c->stream));
+    c->timing_end(2, t0);
     return AD_OK;
   }
   for (int q = 0; q < n; ++q)
@@ -487,10 +498,13 @@ extern "C" int ad_local_search(ad_ctx *c, const ad_batch *b, int n, const int *l
   float *d_e = (float *)(blk + nb_idx + nb_geo);
   HIP_TRY(c, hipMemcpyAsync(d_idx, lig_idx, (size_t)n * 4, hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipMemcpyAsync(d_geo, genotypes, (size_t)n * kStride * 4, hipMemcpyHostToDevice, c->stream));
+  const int t0 = c->timing_begin(2);
   HIP_TRY(c, launch_local_search(C, b->cap, n, d_idx, d_geo, d_e, iters, p->rho, p->eps, c->stream));
+  c->timing_end(2, t0);
   HIP_TRY(c, hipMemcpyAsync(genotypes, d_geo, (size_t)n * kStride * 4, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipMemcpyAsync(energy, d_e, (size_t)n * 4, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->timing_collect();
   return AD_OK;
 }
 
@@ -559,3 +573,65 @@ void fill_map_build_args(void *out, const ad_forcefield &ff, const ad_grid_desc 
 }  // namespace ad
 
 // Docking entry points are implemented in dock.cpp.
+
+// ---------------------------------------------------------------------------
+// kernel timing
+// ---------------------------------------------------------------------------
+int ad_ctx::timing_begin(int kind) {
+  if (!timing) return -1;
+  while (ev_used + 2 > ev_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return -1;
+    ev_pool.push_back(e);
+  }
+  const int s = (int)ev_used;
+  ev_used += 2;
+  if (hipEventRecord(ev_pool[s], stream) != hipSuccess) return -1;
+  (void)kind;
+  return s;
+}
+
+void ad_ctx::timing_end(int kind, int start) {
+  if (start < 0) return;
+  if (hipEventRecord(ev_pool[start + 1], stream) != hipSuccess) return;
+  ev_pending[kind].push_back({start, start + 1});
+}
+
+void ad_ctx::timing_collect() {
+  if (ev_used == 0) return;
+  hipStreamSynchronize(stream);
+  for (int k = 0; k < AD_KERNEL_KINDS; ++k) {
+    for (auto &pr : ev_pending[k]) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, ev_pool[pr.first], ev_pool[pr.second]) == hipSuccess) {
+        t_ms[k] += ms;
+        t_launches[k] += 1;
+      }
+    }
+    ev_pending[k].clear();
+  }
+  ev_used = 0;
+}
+
+extern "C" int ad_set_kernel_timing(ad_ctx *c, int enable) {
+  if (!c) return AD_E_INVALID;
+  hipSetDevice(c->device);
+  c->timing_collect();
+  c->timing = enable != 0;
+  return AD_OK;
+}
+
+extern "C" int ad_get_kernel_timing(ad_ctx *c, ad_kernel_times *out, int reset) {
+  if (!c || !out) return AD_E_INVALID;
+  hipSetDevice(c->device);
+  c->timing_collect();
+  for (int k = 0; k < AD_KERNEL_KINDS; ++k) {
+    out->ms[k] = c->t_ms[k];
+    out->launches[k] = c->t_launches[k];
+    if (reset) {
+      c->t_ms[k] = 0;
+      c->t_launches[k] = 0;
+    }
+  }
+  return AD_OK;
+}

@@ -32,6 +32,23 @@ struct MapBuildArgs {
   float *soa;    // [n_maps+2][nz][ny][nx] or null
 };
 
+struct DockArgs {
+  float *geno;
+  float *energy;
+  unsigned long long *evals;
+  const int *run_order;
+  const uint32_t *lig_id;
+  int n_runs, nrun, pop, n_ls, ls_iters;
+  uint32_t k0, k1;
+  double cx_rate, mut_rate, tour_p, rho, eps, mut_t, mut_theta, mut_rot;
+};
+
+hipError_t launch_dock_init(const EvalConst &C, int cap, const DockArgs &D, hipStream_t s);
+hipError_t launch_ga_generation(const EvalConst &C, int cap, const DockArgs &D, int gen, hipStream_t s);
+hipError_t launch_ls_generation(const EvalConst &C, int cap, const DockArgs &D, int gen, hipStream_t s);
+hipError_t launch_dock_finalize(const DockArgs &D, int buf, float *best_E, float *best_G, hipStream_t s);
+hipError_t launch_init_genotypes(const GridArgs &G, int n_tor, uint32_t k0, uint32_t k1, uint32_t lig_id, int run,
+                                 int pop, float *out, hipStream_t s);
 hipError_t launch_score(const EvalConst &C, int cap, int n, const int *lig_idx, const float *geno, float *E, float *G,
                         float *T, hipStream_t s);
 hipError_t launch_local_search(const EvalConst &C, int cap, int n, const int *lig_idx, float *geno, float *E,
@@ -52,6 +69,7 @@ struct ad_batch {
   ad::PairRec *pairs = nullptr;
   ad::TorRec *tors = nullptr;
   std::vector<ad::LigDesc> lig_host;
+  std::vector<int> depth_sum;
   int map_of_type[AD_MAX_TYPES];   // map index of each type used by the batch at load time (-1: unused)
 };
 
@@ -76,12 +94,23 @@ struct ad_ctx {
   // grow-only scratch buffers
   void *scratch[kScratchSlots] = {nullptr, nullptr, nullptr, nullptr};
   size_t scratch_bytes[kScratchSlots] = {0, 0, 0, 0};
+  // kernel timing (HIP events around launches on `stream`)
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, int>> ev_pending[AD_KERNEL_KINDS];   // (start, stop) pool indices
+  size_t ev_used = 0;
+  double t_ms[AD_KERNEL_KINDS] = {0, 0, 0, 0};
+  int64_t t_launches[AD_KERNEL_KINDS] = {0, 0, 0, 0};
   // docking state buffers
   void *dock_buf = nullptr;
   size_t dock_bytes = 0;
   std::string err;
 
   int fail(int code, const std::string &msg);
+  // timing helpers: mark() before / after a launch of `kind`; collect() after a sync
+  int timing_begin(int kind);
+  void timing_end(int kind, int start);
+  void timing_collect();
   int hip_fail(hipError_t e, const char *where);
   void *scratch_alloc(size_t bytes, int slot);
   ad::EvalConst eval_const(const ad_batch *b) const;

@@ -479,7 +479,7 @@ template <int CAP>
 __device__ void adadelta_wave(const EvalConst &C, const LaneLig<CAP> &LL, EvalLds<CAP> &S, int lane, float *geno_io,
                               float *E_io, int iters, double rho, double eps) {
   const int T = LL.L.n_tor;
-  double gene = lane < kStride ? (double)geno_io[lane] : 0.0;
+  double gene = lane < kStride ? (double)geno_io[lane] : 0.0;   // reads FP32 genes
   double best_gene = gene, best_E = INFINITY;
   double Eg2 = 0.0, Edx2 = 0.0;
   const bool dof = lane < 6 || (lane >= 7 && lane < 7 + T);
@@ -505,6 +505,9 @@ __device__ void adadelta_wave(const EvalConst &C, const LaneLig<CAP> &LL, EvalLd
     else if (lane == 5) gene = qn.y;
     else if (lane == 6) gene = qn.z;
     else if (lane < 7 + T) gene = wrap_angle(gene + dx);
+    // genotypes stay FP32-representable: the stored best pose is exactly the
+    // evaluated one
+    gene = (double)(float)gene;
     __syncthreads();
   }
   if (lane < kStride) geno_io[lane] = (float)best_gene;
@@ -526,6 +529,223 @@ __global__ __launch_bounds__(64) void k_local_search(EvalConst C, int n, const i
   LaneLig<CAP> LL;
   LL.load(C, li, lane);
   adadelta_wave<CAP>(C, LL, S, lane, geno + (size_t)p * kStride, E + p, iters, rho, eps);
+}
+
+// ---------------------------------------------------------------------------
+// Lamarckian GA on the GPU.  Population state per run R (ligand * nrun +
+// run): genotypes [2][n_runs][pop][40] (ping-pong by generation parity) and
+// energies [2][n_runs][pop].  Every genotype stored is exactly the one that
+// was evaluated (genes are rounded to FP32 before evaluation).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ size_t pop_off(const DockArgs &D, int buf, int R) {
+  return ((size_t)buf * D.n_runs + R) * D.pop;
+}
+
+__device__ __forceinline__ float round_gene(double v) { return (float)v; }
+
+// Draw the generation-0 individual `indiv` of (lig id, run): genes on lanes.
+__device__ double init_gene(const GridArgs &G, const Rng &rng, int indiv, int lane, int n_tor) {
+  const double PI = 3.14159265358979323846;
+  double gene = 0.0;
+  if (lane < 3) {
+    const double o = lane == 0 ? G.ox : (lane == 1 ? G.oy : G.oz);
+    const int n = lane == 0 ? G.nx : (lane == 1 ? G.ny : G.nz);
+    gene = o + unif(rng.word(indiv, kStInit, lane)) * G.h * (double)(n - 1);
+  }
+  // orientation by Shoemake's method (every lane computes it; lanes 3-6 keep a component)
+  const uint4 b = rng.block(indiv, kStInit, 0);
+  const uint4 b1 = rng.block(indiv, kStInit, 1);
+  const double u1 = unif(b.w), u2 = unif(b1.x), u3 = unif(b1.y);
+  const double a = sqrt(1.0 - u1), c = sqrt(u1);
+  double s2, c2, s3, c3;
+  sincos(2.0 * PI * u2, &s2, &c2);
+  sincos(2.0 * PI * u3, &s3, &c3);
+  if (lane == 3) gene = a * s2;
+  if (lane == 4) gene = a * c2;
+  if (lane == 5) gene = c * s3;
+  if (lane == 6) gene = c * c3;
+  if (lane >= 7 && lane < 7 + n_tor) gene = -PI + 2.0 * PI * unif(rng.word(indiv, kStInit, 6 + (lane - 7)));
+  return gene;
+}
+
+template <int CAP>
+__global__ __launch_bounds__(64) void k_init_pop(EvalConst C, DockArgs D) {
+  __shared__ EvalLds<CAP> S;
+  const int lane = threadIdx.x;
+  const int R = D.run_order[blockIdx.x / D.pop];
+  const int i = blockIdx.x % D.pop;
+  const int li = R / D.nrun, run = R % D.nrun;
+  LaneLig<CAP> LL;
+  LL.load(C, li, lane);
+  const Rng rng{D.k0, D.k1, D.lig_id[li], (uint32_t)run, 0u};
+  const float g = round_gene(init_gene(C.grid, rng, i, lane, LL.L.n_tor));
+  if (lane < kStride) S.geno[lane] = (double)g;
+  __syncthreads();
+  const double E = evaluate<CAP, false>(C, LL, S, lane, nullptr, nullptr);
+  const size_t off = pop_off(D, 0, R) + i;
+  if (lane < kStride) D.geno[off * kStride + lane] = g;
+  if (lane == 0) {
+    D.energy[off] = (float)E;
+    atomicAdd(&D.evals[R], 1ull);
+  }
+}
+
+// lowest energy (lowest index on ties; NaN ranks as +inf) over a population
+__device__ int wave_argmin(const float *E, int pop, int lane) {
+  float bv = INFINITY;
+  int bi = 0x7fffffff;
+  for (int j = lane; j < pop; j += 64) {
+    float v = E[j];
+    if (!(v == v)) v = INFINITY;
+    if (v < bv || (v == bv && j < bi)) {
+      bv = v;
+      bi = j;
+    }
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const float ov = __shfl_xor(bv, off);
+    const int oi = __shfl_xor(bi, off);
+    if (ov < bv || (ov == bv && oi < bi)) {
+      bv = ov;
+      bi = oi;
+    }
+  }
+  return bi == 0x7fffffff ? 0 : bi;
+}
+
+__device__ __forceinline__ int tournament(const float *E, int pop, double tour_p, uint32_t w0, uint32_t w1,
+                                          uint32_t w2) {
+  const int a = (int)randint(w0, (uint32_t)pop), b = (int)randint(w1, (uint32_t)pop);
+  const float ea = E[a], eb = E[b];
+  const int better = (ea < eb || (ea == eb && a < b)) ? a : b;
+  const int worse = better == a ? b : a;
+  return unif(w2) < tour_p ? better : worse;
+}
+
+// One GA generation `gen` (>= 1): individual 0 keeps the previous best,
+// the others are tournament / crossover / mutation children, evaluated.
+template <int CAP>
+__global__ __launch_bounds__(64) void k_ga_generation(EvalConst C, DockArgs D, int gen) {
+  __shared__ EvalLds<CAP> S;
+  const int lane = threadIdx.x;
+  const int R = D.run_order[blockIdx.x / D.pop];
+  const int i = blockIdx.x % D.pop;
+  const int li = R / D.nrun, run = R % D.nrun;
+  const int src = (gen - 1) & 1, dst = gen & 1;
+  const float *oldG = D.geno + pop_off(D, src, R) * kStride;
+  const float *oldE = D.energy + pop_off(D, src, R);
+  float *newG = D.geno + pop_off(D, dst, R) * kStride;
+  float *newE = D.energy + pop_off(D, dst, R);
+  if (i == 0) {
+    const int b = wave_argmin(oldE, D.pop, lane);
+    if (lane < kStride) newG[lane] = oldG[(size_t)b * kStride + lane];
+    if (lane == 0) newE[0] = oldE[b];
+    return;
+  }
+  LaneLig<CAP> LL;
+  LL.load(C, li, lane);
+  const int T = LL.L.n_tor;
+  const Rng rng{D.k0, D.k1, D.lig_id[li], (uint32_t)run, (uint32_t)gen};
+  const uint4 s0 = rng.block(i, kStSelect, 0), s1 = rng.block(i, kStSelect, 1);
+  const int A = tournament(oldE, D.pop, D.tour_p, s0.x, s0.y, s0.z);
+  const int B = tournament(oldE, D.pop, D.tour_p, s0.w, s1.x, s1.y);
+  // two-point crossover over gene blocks {t, q, theta_0..theta_{T-1}}
+  const uint4 cx = rng.block(i, kStCross, 0);
+  const int nb = 2 + T;
+  int lo = 1, hi = 0;   // empty range
+  if (unif(cx.x) < D.cx_rate) {
+    const int c1 = (int)randint(cx.y, (uint32_t)nb), c2 = (int)randint(cx.z, (uint32_t)nb);
+    lo = min(c1, c2);
+    hi = max(c1, c2);
+  }
+  const int blk = lane < 3 ? 0 : (lane < 7 ? 1 : 2 + (lane - 7));
+  const bool fromB = blk >= lo && blk <= hi;
+  double gene = lane < kStride ? (double)(fromB ? oldG[(size_t)B * kStride + lane] : oldG[(size_t)A * kStride + lane])
+                               : 0.0;
+  // mutation: slot s uses Philox block s of the mutation stream
+  const uint4 mo = rng.block(i, kStMutate, 3);   // orientation slot
+  if (unif(mo.x) < D.mut_rate) {
+    const double PI = 3.14159265358979323846;
+    const double z = 2.0 * unif(mo.y) - 1.0, phi = 2.0 * PI * unif(mo.z), rho = sqrt(1.0 - z * z);
+    const double ang = (2.0 * unif(mo.w) - 1.0) * D.mut_rot;
+    double sp, cp;
+    sincos(phi, &sp, &cp);
+    Q4 q = {__shfl(gene, 3), __shfl(gene, 4), __shfl(gene, 5), __shfl(gene, 6)};
+    Q4 qn = apply_rotvec(q, ang * rho * cp, ang * rho * sp, ang * z);
+    if (lane == 3) gene = qn.w;
+    if (lane == 4) gene = qn.x;
+    if (lane == 5) gene = qn.y;
+    if (lane == 6) gene = qn.z;
+  }
+  if (lane < 3 || (lane >= 7 && lane < 7 + T)) {
+    const int slot = lane < 3 ? lane : 4 + (lane - 7);
+    const uint4 m = rng.block(i, kStMutate, slot);
+    if (unif(m.x) < D.mut_rate) {
+      const double d = 2.0 * unif(m.y) - 1.0;
+      gene = lane < 3 ? gene + d * D.mut_t : wrap_angle(gene + d * D.mut_theta);
+    }
+  }
+  const float g = round_gene(gene);
+  if (lane < kStride) S.geno[lane] = (double)g;
+  __syncthreads();
+  const double E = evaluate<CAP, false>(C, LL, S, lane, nullptr, nullptr);
+  if (lane < kStride) newG[(size_t)i * kStride + lane] = g;
+  if (lane == 0) {
+    newE[i] = (float)E;
+    atomicAdd(&D.evals[R], 1ull);
+  }
+}
+
+// ADADELTA on the individuals picked for generation `gen`: n_ls distinct
+// indices from 1..pop-1 by a partial Fisher-Yates shuffle (word s of the
+// pick stream draws the partner of position s).  Dynamic LDS: pop ints.
+template <int CAP>
+__global__ __launch_bounds__(64) void k_ls_generation(EvalConst C, DockArgs D, int gen) {
+  __shared__ EvalLds<CAP> S;
+  extern __shared__ int perm[];
+  const int lane = threadIdx.x;
+  const int R = D.run_order[blockIdx.x / D.n_ls];
+  const int slot = blockIdx.x % D.n_ls;
+  const int li = R / D.nrun, run = R % D.nrun;
+  const int m = D.pop - 1;
+  for (int j = lane; j < m; j += 64) perm[j] = j + 1;
+  __syncthreads();
+  const Rng rng{D.k0, D.k1, D.lig_id[li], (uint32_t)run, (uint32_t)gen};
+  if (lane == 0) {
+    for (int s = 0; s <= slot; ++s) {
+      const int r = s + (int)randint(rng.word(0, kStLsPick, s), (uint32_t)(m - s));
+      const int t = perm[s];
+      perm[s] = perm[r];
+      perm[r] = t;
+    }
+  }
+  __syncthreads();
+  const int indiv = perm[slot];
+  LaneLig<CAP> LL;
+  LL.load(C, li, lane);
+  const size_t off = pop_off(D, gen & 1, R) + indiv;
+  adadelta_wave<CAP>(C, LL, S, lane, D.geno + off * kStride, D.energy + off, D.ls_iters, D.rho, D.eps);
+  if (lane == 0) atomicAdd(&D.evals[R], (unsigned long long)D.ls_iters);
+}
+
+// Best individual of every run after the last generation.
+__global__ __launch_bounds__(64) void k_finalize(DockArgs D, int buf, float *best_E, float *best_G) {
+  const int lane = threadIdx.x;
+  const int R = blockIdx.x;
+  const float *E = D.energy + pop_off(D, buf, R);
+  const int b = wave_argmin(E, D.pop, lane);
+  if (lane < kStride) best_G[(size_t)R * kStride + lane] = D.geno[(pop_off(D, buf, R) + b) * kStride + lane];
+  if (lane == 0) best_E[R] = E[b];
+}
+
+// Generation-0 genotypes only (diagnostics).
+__global__ __launch_bounds__(64) void k_init_genotypes(GridArgs G, int n_tor, uint32_t k0, uint32_t k1,
+                                                       uint32_t lig_id, int run, float *out) {
+  const int lane = threadIdx.x, i = blockIdx.x;
+  const Rng rng{k0, k1, lig_id, (uint32_t)run, 0u};
+  const float g = (float)init_gene(G, rng, i, lane, n_tor);
+  if (lane < kStride) out[(size_t)i * kStride + lane] = g;
 }
 
 // ---------------------------------------------------------------------------
@@ -652,5 +872,39 @@ hipError_t launch_relayout(const float *soa, float *out4, size_t nn, int n_maps,
   return hipGetLastError();
 }
 
+
+hipError_t launch_dock_init(const EvalConst &C, int cap, const DockArgs &D, hipStream_t s) {
+  dim3 grid((unsigned)D.n_runs * D.pop), block(64);
+  if (cap <= 64) hipLaunchKernelGGL((k_init_pop<64>), grid, block, 0, s, C, D);
+  else hipLaunchKernelGGL((k_init_pop<128>), grid, block, 0, s, C, D);
+  return hipGetLastError();
+}
+
+hipError_t launch_ga_generation(const EvalConst &C, int cap, const DockArgs &D, int gen, hipStream_t s) {
+  dim3 grid((unsigned)D.n_runs * D.pop), block(64);
+  if (cap <= 64) hipLaunchKernelGGL((k_ga_generation<64>), grid, block, 0, s, C, D, gen);
+  else hipLaunchKernelGGL((k_ga_generation<128>), grid, block, 0, s, C, D, gen);
+  return hipGetLastError();
+}
+
+hipError_t launch_ls_generation(const EvalConst &C, int cap, const DockArgs &D, int gen, hipStream_t s) {
+  dim3 block(64);
+  dim3 lgrid((unsigned)D.n_runs * D.n_ls);
+  size_t dyn = (size_t)D.pop * sizeof(int);
+  if (cap <= 64) hipLaunchKernelGGL((k_ls_generation<64>), lgrid, block, dyn, s, C, D, gen);
+  else hipLaunchKernelGGL((k_ls_generation<128>), lgrid, block, dyn, s, C, D, gen);
+  return hipGetLastError();
+}
+
+hipError_t launch_dock_finalize(const DockArgs &D, int buf, float *best_E, float *best_G, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(D.n_runs), dim3(64), 0, s, D, buf, best_E, best_G);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_genotypes(const GridArgs &G, int n_tor, uint32_t k0, uint32_t k1, uint32_t lig_id, int run,
+                                 int pop, float *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_genotypes, dim3(pop), dim3(64), 0, s, G, n_tor, k0, k1, lig_id, run, out);
+  return hipGetLastError();
+}
 
 }  // namespace ad

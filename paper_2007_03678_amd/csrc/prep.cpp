@@ -196,6 +196,9 @@ int prepare_ligand(const ad_ligand &L, const ad_forcefield &ff, const int *type_
     P.tors[k].depth = d;
     P.max_depth = std::max(P.max_depth, d);
   }
+  // torsions moving each atom, summed over atoms
+  for (int i = 0; i < n; ++i)
+    for (int q = owner[i]; q >= 0; q = P.tors[q].parent) ++P.depth_sum;
   // bond distances by breadth-first search from every atom (n <= 128)
   std::vector<std::vector<int>> dist(n, std::vector<int>(n, -1));
   for (int s0 = 0; s0 < n; ++s0) {

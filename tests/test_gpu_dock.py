@@ -1,0 +1,184 @@
+"""GPU parity of the docking search (Lamarckian GA + ADADELTA) with the oracle.
+
+The search is stochastic and chaotic (a tournament between two close
+energies can go either way in FP32 vs FP64), so parity is checked where it
+is well defined: identical random streams (the initial population), every
+returned pose re-scores to its energy, exact evaluation accounting,
+per-ligand reproducibility from (seed, ligand id), and the distribution of
+best energies over independent seeds (Mann-Whitney U, medians within
+0.3 kcal/mol).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+E_ABS, E_REL = 1e-3, 1e-5
+
+
+@pytest.fixture(scope="module")
+def pkg():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2007_03678_amd as pkg
+    pkg.lib()
+    return pkg
+
+
+@pytest.fixture(scope="module")
+def setup(pkg, ff, orc):
+    rec = synth.receptor(31, 1200, side=16.0)
+    grid = synth.make_grid(32, 0.375, map_types=synth.SIX_TYPES)
+    G = orc.grid(grid, rec)
+    ctx = pkg.create(ff, 0)
+    ctx.ad_load_grids(grid, G.values())
+    yield ctx, grid, G
+    ctx.close()
+
+
+def test_initial_population_matches_oracle_streams(pkg, setup, orc):
+    ctx, grid, G = setup
+    lig = synth.ligand(40, 30, 7)
+    batch = ctx.ad_load_ligands([lig])
+    L = orc.ligand(lig)
+    seed = (123 << 32) | 456
+    gp = ctx.ad_initial_population(batch, 0, 77, 3, 200, seed)
+    for i in range(200):
+        go = orc.init_individual(L, G, seed, 77, 3, i)
+        assert np.allclose(gp[i], go.astype(np.float32), rtol=0, atol=2e-6), i
+    batch.free()
+
+
+def test_local_search_improves_and_rescores(pkg, setup, orc):
+    ctx, grid, G = setup
+    ligs = [synth.ligand(41 + i, n, t) for i, (n, t) in enumerate([(18, 4), (35, 9), (70, 20)])]
+    batch = ctx.ad_load_ligands(ligs)
+    OL = [orc.ligand(l) for l in ligs]
+    n = 96
+    idx = (np.arange(n) % 3).astype(np.int32)
+    ntor = np.array([OL[i].n_tor for i in idx])
+    g0 = synth.random_genotypes(5, n, ntor, grid, margin=3.0, normalize_q=True)
+    E0, _, _ = ctx.ad_score_poses(batch, idx, g0)
+    p = pkg.make_params()
+    g1, E1 = ctx.ad_local_search(batch, idx, g0, p, 100)
+    assert np.all(E1 <= E0)
+    # the returned pose re-scores to the returned energy (GPU and oracle)
+    E1r, _, _ = ctx.ad_score_poses(batch, idx, g1)
+    assert np.array_equal(E1r, E1)
+    Eo, _, _ = orc.score_batch(OL, idx, G, g1)
+    assert np.all(np.abs(E1 - Eo) <= np.maximum(E_ABS, E_REL * np.abs(Eo)))
+    # statistically as good as the FP64 oracle's ADADELTA from the same starts
+    Eorc = np.array([orc.adadelta(OL[i], G, oracle.make_params(), g0[k].astype(np.float64), 100)[1]
+                     for k, i in enumerate(idx)])
+    assert abs(np.median(E1) - np.median(Eorc)) < 0.15 * abs(np.median(Eorc)) + 0.5
+    batch.free()
+
+
+def test_local_search_first_iterations_follow_oracle(pkg, setup, orc):
+    """One and three ADADELTA evaluations from the same start: the GPU keeps the
+    same best pose as the FP64 oracle (the trajectories only drift apart by
+    rounding later)."""
+    ctx, grid, G = setup
+    lig = synth.ligand(45, 25, 6)
+    batch = ctx.ad_load_ligands([lig])
+    L = orc.ligand(lig)
+    g0 = synth.random_genotypes(6, 32, L.n_tor, grid, margin=3.0, normalize_q=True)
+    p = pkg.make_params()
+    for iters in (1, 3):
+        g1, E1 = ctx.ad_local_search(batch, np.zeros(32, np.int32), g0, p, iters)
+        for k in range(32):
+            bo, Eo = orc.adadelta(L, G, oracle.make_params(), g0[k].astype(np.float64), iters)
+            assert abs(E1[k] - Eo) <= max(1e-2, 1e-4 * abs(Eo)), (iters, k, E1[k], Eo)
+            assert np.allclose(g1[k][:3], bo[:3], atol=1e-3)
+    batch.free()
+
+
+def small_params(pkg, **kw):
+    d = dict(nrun=4, pop=30, max_gens=8, ls_rate=0.1, ls_iters=40)
+    d.update(kw)
+    return pkg.make_params(**d)
+
+
+def test_dock_accounting_rescoring_and_reproducibility(pkg, setup, orc):
+    ctx, grid, G = setup
+    ligs = [synth.ligand(50 + i, n, t) for i, (n, t) in enumerate([(12, 2), (26, 6), (44, 12), (66, 18)])]
+    batch = ctx.ad_load_ligands(ligs)
+    OL = [orc.ligand(l) for l in ligs]
+    p = small_params(pkg)
+    seed = 2024
+    r = ctx.ad_dock_batch(batch, p, seed, per_run=True)
+    n_ls = 3
+    per_gen = (30 - 1) + n_ls * 40
+    assert np.all(r["generations"] == 8)
+    assert np.all(r["evals"] == 4 * (30 + 8 * per_gen))
+    # every returned pose re-scores to its energy; the best is the min over runs
+    for l in range(4):
+        assert r["best_energy"][l] == r["run_energy"][l].min()
+        assert r["best_run"][l] == int(np.argmin(r["run_energy"][l]))
+        Eo, _, To = orc.score(OL[l], G, r["best_genotype"][l].astype(np.float64))
+        assert abs(r["best_energy"][l] - Eo) <= max(E_ABS, E_REL * abs(Eo))
+        assert abs(r["best_score"][l] - To[2]) <= max(E_ABS, E_REL * abs(To[2]))
+        Er, _, _ = ctx.ad_score_poses(batch, np.full(4, l, np.int32), r["run_genotype"][l])
+        assert np.array_equal(Er, r["run_energy"][l])
+    # deterministic, and a ligand's result depends only on (seed, its id)
+    r2 = ctx.ad_dock_batch(batch, p, seed, per_run=True)
+    assert np.array_equal(r["run_energy"], r2["run_energy"])
+    assert np.array_equal(r["run_genotype"], r2["run_genotype"])
+    solo = ctx.ad_load_ligands([ligs[2]])
+    r3 = ctx.ad_dock_batch(solo, p, seed, lig_ids=np.array([2], np.uint32), per_run=True)
+    assert np.array_equal(r3["run_energy"][0], r["run_energy"][2])
+    r4 = ctx.ad_dock_batch(batch, p, seed + 1, per_run=True)
+    assert not np.array_equal(r4["run_energy"], r["run_energy"])
+    # the search improves on the initial population
+    init = np.array([[ctx.ad_score_poses(batch, np.full(30, l, np.int32),
+                                         ctx.ad_initial_population(batch, l, l, run, 30, seed))[0].min()
+                      for run in range(4)] for l in range(4)])
+    assert np.all(r["run_energy"] <= init)
+    assert np.mean(r["run_energy"] < init - 1.0) > 0.5
+    solo.free()
+    batch.free()
+
+
+def test_dock_parameter_errors(pkg, setup):
+    ctx, grid, G = setup
+    batch = ctx.ad_load_ligands([synth.ligand(60, 10, 2)])
+    for kw, code in [(dict(pop=1), pkg.AD_E_INVALID), (dict(pop=5000), pkg.AD_E_INVALID),
+                     (dict(ls_rate=1.5), pkg.AD_E_INVALID), (dict(rho=1.0), pkg.AD_E_INVALID),
+                     (dict(autostop=1), pkg.AD_E_UNSUPPORTED), (dict(ls_method=1), pkg.AD_E_UNSUPPORTED),
+                     (dict(nrun=0), pkg.AD_E_INVALID)]:
+        with pytest.raises(pkg.AddockError) as e:
+            ctx.ad_dock_batch(batch, small_params(pkg, **kw), 1)
+        assert e.value.code == code, kw
+    # zero generations: only the initial population
+    r = ctx.ad_dock_batch(batch, small_params(pkg, max_gens=0), 1)
+    assert r["generations"][0] == 0 and r["evals"][0] == 4 * 30
+    batch.free()
+
+
+def test_docking_statistics_match_oracle(pkg, ff, orc):
+    """Single-ligand workload (24 atoms, 5 torsions; 4 runs x pop 50 x 50
+    generations, ADADELTA 300 iterations on 6%), 48 independent random
+    streams (ligand ids): GPU and oracle best-energy distributions agree."""
+    from scipy.stats import mannwhitneyu
+    c = synth.config("single24")
+    grid, rec = c["grid"], c["receptor"]
+    lig = c["ligands"][0]
+    G = orc.grid(grid, rec)
+    ctx = pkg.create(ff, 0)
+    ctx.ad_load_grids(grid, G.values())
+    n_seeds = 48
+    batch = ctx.ad_load_ligands([lig] * n_seeds)
+    kw = dict(nrun=4, pop=50, max_gens=50, ls_rate=0.06, ls_iters=300)
+    r = ctx.ad_dock_batch(batch, pkg.make_params(**kw), 7)
+    L = orc.ligand(lig)
+    po = oracle.make_params(**kw)
+    eo = np.array([orc.dock(L, G, po, 7, k)[1].min() for k in range(n_seeds)])
+    eg = r["best_energy"].astype(np.float64)
+    p = mannwhitneyu(eg, eo).pvalue
+    assert p > 0.01, (p, np.sort(eg), np.sort(eo))
+    assert abs(np.median(eg) - np.median(eo)) < 0.3 + 0.05 * abs(np.median(eo)), (np.median(eg), np.median(eo))
+    batch.free()
+    ctx.close()
