@@ -39,9 +39,10 @@ struct alignas(16) AtomInfo {
   int type;     // force-field type
 };
 
-// Intramolecular pair: i, j (internal order) and type-pair index packed in
-// one word, with the two pair-specific coefficients precomputed in double
-// and rounded: qq = w_el k_e q_i q_j, dsv = w_sol (S_i V_j + S_j V_i).
+// Intramolecular pair (16 bytes): i, j (internal order) and the type-pair
+// index packed in one word, with the two pair-specific coefficients
+// precomputed in double and rounded: qq = w_el k_e q_i q_j,
+// dsv = w_sol (S_i V_j + S_j V_i).  A ligand's list stays L1-resident.
 struct alignas(16) PairRec {
   uint32_t ijt;   // i | j << 8 | (ti * n_types + tj) << 16
   float qq;

@@ -24,22 +24,89 @@ namespace ad {
 // ---------------------------------------------------------------------------
 // small helpers
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+// Wavefront scans with DPP lane moves (no LDS crossbar round trips): rows of
+// 16 lanes by row_shr 1, 2, 4, 8, then row_bcast 15 / 31 across rows.  The
+// summation order is fixed, so results are bitwise reproducible.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)__double2loint(v), CTRL, ROW_MASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)__double2hiint(v), CTRL, ROW_MASK, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double wave_incl_scan(double v) {
+  v += dpp_f64<0x111, 0xf>(v);   // row_shr:1
+  v += dpp_f64<0x112, 0xf>(v);   // row_shr:2
+  v += dpp_f64<0x114, 0xf>(v);   // row_shr:4
+  v += dpp_f64<0x118, 0xf>(v);   // row_shr:8
+  v += dpp_f64<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+  v += dpp_f64<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
   return v;
 }
 
-__device__ __forceinline__ double wave_incl_scan(double v, int lane) {
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    double o = __shfl_up(v, off);
-    if (lane >= off) v += o;
-  }
-  return v;
+// value of lane 63 (uniform)
+__device__ __forceinline__ double wave_last(double v) {
+  const int lo = __builtin_amdgcn_readlane((int)__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane((int)__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double wave_sum(double v) { return wave_last(wave_incl_scan(v)); }
+
+__device__ __forceinline__ float lane_f32(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 
 __device__ __forceinline__ float fast_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+
+// sin and cos of an FP64 angle.  Cody-Waite reduction by pi/2 (pi/2 split into
+// 33 + 33 + 53 significant bits, so k*C1 and k*C2 are exact for |k| < 2^20)
+// to r in [-pi/4, pi/4], then the Taylor series of sin (through r^17) and cos
+// (through r^16) in Horner form: truncation below 1e-17 on that interval.
+// Arguments beyond 1e5 rad take the library routine.
+__device__ __forceinline__ void sincos_f64(double x, double *sn, double *cs) {
+  if (!(fabs(x) <= 1.0e5)) {
+    sincos(x, sn, cs);
+    return;
+  }
+  const double k = rint(x * 0.6366197723675814);
+  double r = fma(-k, 1.5707963267341256, x);
+  r = fma(-k, 6.077100506303966e-11, r);
+  r = fma(-k, 2.0222662487959506e-21, r);
+  const double z = r * r;
+  double ps = 2.8114572543455206e-15;            // 1/17!
+  ps = fma(ps, z, -7.647163731819816e-13);       // -1/15!
+  ps = fma(ps, z, 1.6059043836821613e-10);       // 1/13!
+  ps = fma(ps, z, -2.505210838544172e-08);       // -1/11!
+  ps = fma(ps, z, 2.7557319223985893e-06);       // 1/9!
+  ps = fma(ps, z, -0.0001984126984126984);       // -1/7!
+  ps = fma(ps, z, 0.008333333333333333);         // 1/5!
+  ps = fma(ps, z, -0.16666666666666666);         // -1/3!
+  const double sr = fma(ps * z, r, r);
+  double pc = 4.779477332387385e-14;             // 1/16!
+  pc = fma(pc, z, -1.1470745597729725e-11);      // -1/14!
+  pc = fma(pc, z, 2.08767569878681e-09);         // 1/12!
+  pc = fma(pc, z, -2.755731922398589e-07);       // -1/10!
+  pc = fma(pc, z, 2.48015873015873e-05);         // 1/8!
+  pc = fma(pc, z, -0.001388888888888889);        // -1/6!
+  pc = fma(pc, z, 0.041666666666666664);         // 1/4!
+  pc = fma(pc, z, -0.5);                         // -1/2!
+  const double cr = fma(pc, z, 1.0);
+  const int q = ((int)k) & 3;
+  const double s0 = (q & 1) ? cr : sr;
+  const double c0 = (q & 1) ? sr : cr;
+  *sn = (q & 2) ? -s0 : s0;
+  *cs = ((q + 1) & 2) ? -c0 : c0;
+}
+
+// 1/sqrt(a) in FP64: hardware estimate refined by two Newton steps.
+__device__ __forceinline__ double rsqrt_f64(double a) {
+  double y = __builtin_amdgcn_rsq(a);
+  const double h = 0.5 * a;
+  y = y * fma(-h * y, y, 1.5);
+  y = y * fma(-h * y, y, 1.5);
+  return y;
+}
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 
@@ -115,58 +182,24 @@ struct EvalLds {
   double x[CAP][3];   // posed coordinates
   double g[CAP][3];   // dE/dx accumulators
   union {
-    double tm[kMaxTor][12];   // composite rigid transforms of the fragments (pose phase)
+    double tm[kMaxTor][12];   // torsion rigid transforms T_k = (R_k | w_k) (pose phase)
     double pre[CAP][6];       // inclusive prefix sums of (g, (x-t) x g) (gradient phase)
   };
+  int tpar[kMaxTor];          // parent torsion of each torsion (-1: root fragment)
   double geno[kStride];        // genotype being evaluated
   double grad[kStride];        // output gradient
+  double rot[9];               // global rotation matrix of the pose
 };
 
-// Per-lane ligand data that stays in registers across evaluations.
+// Ligand being evaluated.  Per-atom and per-torsion records are re-read from
+// L1-resident global memory inside every evaluation instead of being held in
+// registers across a local search's iterations (register pressure decides
+// how many wavefronts share a SIMD).
 template <int CAP>
 struct LaneLig {
   static constexpr int APL = CAP / 64;
   LigDesc L;
-  double y[APL][3];
-  float q[APL];
-  int map[APL];
-  int owner[APL];
-  // torsion lane data (lane < n_tor)
-  double to[3], tu[3], tinv_len;
-  int tparent, ts, te, ta, tb, tdepth;
-
-  __device__ void load(const EvalConst &C, int li, int lane) {
-    L = C.batch.lig[li];
-#pragma unroll
-    for (int c = 0; c < APL; ++c) {
-      int i = c * 64 + lane;
-      if (i < L.n_atoms) {
-        const AtomGeo &gq = C.batch.geo[L.atom_off + i];
-        const AtomInfo &in = C.batch.info[L.atom_off + i];
-        y[c][0] = gq.y[0];
-        y[c][1] = gq.y[1];
-        y[c][2] = gq.y[2];
-        q[c] = in.q;
-        map[c] = in.map;
-        owner[c] = in.owner;
-      } else {
-        y[c][0] = y[c][1] = y[c][2] = 0;
-        q[c] = 0;
-        map[c] = 0;
-        owner[c] = -1;
-      }
-    }
-    if (lane < L.n_tor) {
-      const TorRec &t = C.batch.tors[L.tor_off + lane];
-      to[0] = t.o[0]; to[1] = t.o[1]; to[2] = t.o[2];
-      tu[0] = t.u[0]; tu[1] = t.u[1]; tu[2] = t.u[2];
-      tinv_len = t.inv_len;
-      tparent = t.parent; ts = t.s; te = t.e; ta = t.a; tb = t.b; tdepth = t.depth;
-    } else {
-      to[0] = to[1] = to[2] = tu[0] = tu[1] = tu[2] = tinv_len = 0;
-      tparent = -1; ts = te = ta = tb = 0; tdepth = 0;
-    }
-  }
+  __device__ void load(const EvalConst &C, int li, int lane) { L = C.batch.lig[li]; }
 };
 
 // Trilinear interpolation of map_m + q map_e + |q| map_d with its gradient,
@@ -226,7 +259,7 @@ __device__ __forceinline__ double grid_energy(const GridArgs &G, double k_out, i
 }
 
 // One intramolecular pair in FP32: returns the energy, writes dE/dr / r.
-__device__ __forceinline__ float pair_energy(const FFConst &K, const LJRec lj, float qq, float dsv, float r2,
+__device__ __forceinline__ float pair_energy(const FFConst &K, const LJRec &lj, float qq, float dsv, float r2,
                                              float *fscale) {
   const bool floored = !(r2 >= K.r_floor2);
   const float r2c = floored ? K.r_floor2 : r2;
@@ -281,66 +314,68 @@ __device__ double evaluate(const EvalConst &C, const LaneLig<CAP> &LL, EvalLds<C
                            double *intra_out) {
   constexpr int APL = CAP / 64;
   const LigDesc &L = LL.L;
-  // global rigid transform: x = R (y) + t, y relative to the centre
+  // keep the ligand records below from being hoisted out of a caller's loop
+  asm volatile("" ::: "memory");
+  // global rigid transform x = R y + t (y relative to the centre): R from the
+  // normalised quaternion, one element per lane, kept in LDS
   const double t0 = S.geno[0], t1 = S.geno[1], t2 = S.geno[2];
-  Q4 q = qnormalize({S.geno[3], S.geno[4], S.geno[5], S.geno[6]});
-  double R[9] = {1 - 2 * (q.y * q.y + q.z * q.z), 2 * (q.x * q.y - q.w * q.z), 2 * (q.x * q.z + q.w * q.y),
-                 2 * (q.x * q.y + q.w * q.z), 1 - 2 * (q.x * q.x + q.z * q.z), 2 * (q.y * q.z - q.w * q.x),
-                 2 * (q.x * q.z - q.w * q.y), 2 * (q.y * q.z + q.w * q.x), 1 - 2 * (q.x * q.x + q.y * q.y)};
-  // torsion transforms T_k(y) = Rk (y - o) + o, composed root-ward level by
-  // level: C_k = C_parent o T_k with C_root = global transform
-  double Rk[9], wk[3];
+  if (lane < 9) {
+    const double qw0 = S.geno[3], qx0 = S.geno[4], qy0 = S.geno[5], qz0 = S.geno[6];
+    const double inv = rsqrt_f64(qw0 * qw0 + qx0 * qx0 + qy0 * qy0 + qz0 * qz0);
+    const double w = qw0 * inv, x = qx0 * inv, y = qy0 * inv, z = qz0 * inv;
+    double v;
+    switch (lane) {
+      case 0: v = 1 - 2 * (y * y + z * z); break;
+      case 1: v = 2 * (x * y - w * z); break;
+      case 2: v = 2 * (x * z + w * y); break;
+      case 3: v = 2 * (x * y + w * z); break;
+      case 4: v = 1 - 2 * (x * x + z * z); break;
+      case 5: v = 2 * (y * z - w * x); break;
+      case 6: v = 2 * (x * z - w * y); break;
+      case 7: v = 2 * (y * z + w * x); break;
+      default: v = 1 - 2 * (x * x + y * y); break;
+    }
+    S.rot[lane] = v;
+  }
+  // torsion transforms T_k(y) = R_k (y - o_k) + o_k in the reference frame
   if (lane < L.n_tor) {
-    double s, c;
-    sincos(S.geno[7 + lane], &s, &c);
-    rot_matrix(LL.tu, c, s, Rk);
+    const TorRec &tr = C.batch.tors[L.tor_off + lane];
+    const double to[3] = {tr.o[0], tr.o[1], tr.o[2]};
+    const double tu[3] = {tr.u[0], tr.u[1], tr.u[2]};
+    double sn, cs, Rk[9];
+    sincos_f64(S.geno[7 + lane], &sn, &cs);
+    rot_matrix(tu, cs, sn, Rk);
+#pragma unroll
+    for (int e = 0; e < 9; ++e) S.tm[lane][e] = Rk[e];
 #pragma unroll
     for (int r = 0; r < 3; ++r)
-      wk[r] = LL.to[r] - (Rk[3 * r] * LL.to[0] + Rk[3 * r + 1] * LL.to[1] + Rk[3 * r + 2] * LL.to[2]);
+      S.tm[lane][9 + r] = to[r] - (Rk[3 * r] * to[0] + Rk[3 * r + 1] * to[1] + Rk[3 * r + 2] * to[2]);
+    S.tpar[lane] = tr.parent;
   }
-  for (int level = 1; level <= L.max_depth; ++level) {
-    if (lane < L.n_tor && LL.tdepth == level) {
-      double M[12];
-      if (LL.tparent < 0) {
-#pragma unroll
-        for (int e = 0; e < 9; ++e) M[e] = R[e];
-        M[9] = t0; M[10] = t1; M[11] = t2;
-      } else {
-#pragma unroll
-        for (int e = 0; e < 12; ++e) M[e] = S.tm[LL.tparent][e];
-      }
-      double out[12];
-#pragma unroll
-      for (int r = 0; r < 3; ++r) {
-#pragma unroll
-        for (int cc = 0; cc < 3; ++cc)
-          out[3 * r + cc] = M[3 * r] * Rk[cc] + M[3 * r + 1] * Rk[3 + cc] + M[3 * r + 2] * Rk[6 + cc];
-        out[9 + r] = M[3 * r] * wk[0] + M[3 * r + 1] * wk[1] + M[3 * r + 2] * wk[2] + M[9 + r];
-      }
-#pragma unroll
-      for (int e = 0; e < 12; ++e) S.tm[lane][e] = out[e];
-    }
-    __syncthreads();
-  }
+  __syncthreads();
   // atoms: pose and inter-molecular energy
   double e_inter = 0.0;
 #pragma unroll
   for (int c = 0; c < APL; ++c) {
     const int i = c * 64 + lane;
     if (i < L.n_atoms) {
-      const double *yy = LL.y[c];
-      double x[3];
-      if (LL.owner[c] < 0) {
-#pragma unroll
-        for (int r = 0; r < 3; ++r) x[r] = R[3 * r] * yy[0] + R[3 * r + 1] * yy[1] + R[3 * r + 2] * yy[2];
-        x[0] += t0; x[1] += t1; x[2] += t2;
-      } else {
-        const double *M = S.tm[LL.owner[c]];
-#pragma unroll
-        for (int r = 0; r < 3; ++r) x[r] = M[3 * r] * yy[0] + M[3 * r + 1] * yy[1] + M[3 * r + 2] * yy[2] + M[9 + r];
+      const AtomGeo &ag = C.batch.geo[L.atom_off + i];
+      const AtomInfo &ai = C.batch.info[L.atom_off + i];
+      // torsions moving the atom, deepest first, then the global transform
+      double y0 = ag.y[0], y1 = ag.y[1], y2 = ag.y[2];
+      for (int k = ai.owner; k >= 0; k = S.tpar[k]) {
+        const double *M = S.tm[k];
+        const double n0 = fma(M[0], y0, fma(M[1], y1, fma(M[2], y2, M[9])));
+        const double n1 = fma(M[3], y0, fma(M[4], y1, fma(M[5], y2, M[10])));
+        const double n2 = fma(M[6], y0, fma(M[7], y1, fma(M[8], y2, M[11])));
+        y0 = n0; y1 = n1; y2 = n2;
       }
+      double x[3];
+#pragma unroll
+      for (int r = 0; r < 3; ++r) x[r] = S.rot[3 * r] * y0 + S.rot[3 * r + 1] * y1 + S.rot[3 * r + 2] * y2;
+      x[0] += t0; x[1] += t1; x[2] += t2;
       double g[3];
-      e_inter += grid_energy(C.grid, C.ff.k_out, LL.map[c], LL.q[c], x, g);
+      e_inter += grid_energy(C.grid, C.ff.k_out, ai.map, ai.q, x, g);
       S.x[i][0] = x[0]; S.x[i][1] = x[1]; S.x[i][2] = x[2];
       if (GRAD) { S.g[i][0] = g[0]; S.g[i][1] = g[1]; S.g[i][2] = g[2]; }
     }
@@ -353,10 +388,11 @@ __device__ double evaluate(const EvalConst &C, const LaneLig<CAP> &LL, EvalLds<C
   for (int p = lane; p < L.n_pairs; p += 64) {
     const PairRec rec = pr[p];
     const int i = rec.ijt & 0xff, j = (rec.ijt >> 8) & 0xff, tp = rec.ijt >> 16;
+    const LJRec lj = ljt[tp];
     const double dx = S.x[i][0] - S.x[j][0], dy = S.x[i][1] - S.x[j][1], dz = S.x[i][2] - S.x[j][2];
     const float r2 = (float)(dx * dx + dy * dy + dz * dz);
     float fs;
-    e_intra += (double)pair_energy(C.ff, ljt[tp], rec.qq, rec.dsv, r2, &fs);
+    e_intra += (double)pair_energy(C.ff, lj, rec.qq, rec.dsv, r2, &fs);
     if (GRAD) {
       const double f = (double)fs;
       atomicAdd(&S.g[i][0], f * dx);
@@ -397,9 +433,9 @@ __device__ double evaluate(const EvalConst &C, const LaneLig<CAP> &LL, EvalLds<C
     const int i = c * 64 + lane;
 #pragma unroll
     for (int e = 0; e < 6; ++e) {
-      double s = wave_incl_scan(vv[c][e], lane) + carry[e];
+      double s = wave_incl_scan(vv[c][e]) + carry[e];
       if (i < L.n_atoms) S.pre[i][e] = s;
-      carry[e] = __shfl(s, 63);
+      carry[e] = wave_last(s);
     }
   }
   __syncthreads();
@@ -410,17 +446,20 @@ __device__ double evaluate(const EvalConst &C, const LaneLig<CAP> &LL, EvalLds<C
     S.grad[lane] = gv;
   }
   if (lane < L.n_tor) {
+    const TorRec &tr = C.batch.tors[L.tor_off + lane];
+    const int ts = tr.s, te = tr.e, ta = tr.a, tb = tr.b;
+    const double tinv_len = tr.inv_len;
     double F[6];
 #pragma unroll
-    for (int e = 0; e < 6; ++e) F[e] = S.pre[LL.te - 1][e] - (LL.ts > 0 ? S.pre[LL.ts - 1][e] : 0.0);
-    const double ax = S.x[LL.ta][0] - t0, ay = S.x[LL.ta][1] - t1, az = S.x[LL.ta][2] - t2;
+    for (int e = 0; e < 6; ++e) F[e] = S.pre[te - 1][e] - (ts > 0 ? S.pre[ts - 1][e] : 0.0);
+    const double ax = S.x[ta][0] - t0, ay = S.x[ta][1] - t1, az = S.x[ta][2] - t2;
     // torque about the axis point a: sum (x_i - t) x g_i - (x_a - t) x sum g_i
     const double tx = F[3] - (ay * F[2] - az * F[1]);
     const double ty = F[4] - (az * F[0] - ax * F[2]);
     const double tz = F[5] - (ax * F[1] - ay * F[0]);
-    const double ux = (S.x[LL.tb][0] - S.x[LL.ta][0]) * LL.tinv_len;
-    const double uy = (S.x[LL.tb][1] - S.x[LL.ta][1]) * LL.tinv_len;
-    const double uz = (S.x[LL.tb][2] - S.x[LL.ta][2]) * LL.tinv_len;
+    const double ux = (S.x[tb][0] - S.x[ta][0]) * tinv_len;
+    const double uy = (S.x[tb][1] - S.x[ta][1]) * tinv_len;
+    const double uz = (S.x[tb][2] - S.x[ta][2]) * tinv_len;
     S.grad[7 + lane] = ux * tx + uy * ty + uz * tz;
   }
   __syncthreads();
@@ -477,14 +516,20 @@ __global__ __launch_bounds__(64) void k_score(EvalConst C, int n, const int *__r
 // ---------------------------------------------------------------------------
 template <int CAP>
 __device__ void adadelta_wave(const EvalConst &C, const LaneLig<CAP> &LL, EvalLds<CAP> &S, int lane, float *geno_io,
-                              float *E_io, int iters, double rho, double eps) {
+                              float *E_io, int iters, double rho_d, double eps_d) {
   const int T = LL.L.n_tor;
-  double gene = lane < kStride ? (double)geno_io[lane] : 0.0;   // reads FP32 genes
-  double best_gene = gene, best_E = INFINITY;
-  double Eg2 = 0.0, Edx2 = 0.0;
+  // genes are FP32 values; the step arithmetic runs in FP32 with native
+  // square roots (the accumulated squared gradient in FP64: gradients of
+  // clashing poses overflow FP32 when squared)
+  float gene = lane < kStride ? geno_io[lane] : 0.0f;
+  float best_gene = gene;
+  double best_E = INFINITY;
+  double Eg2 = 0.0;
+  float Edx2 = 0.0f;
+  const float rho = (float)rho_d, eps = (float)eps_d;
   const bool dof = lane < 6 || (lane >= 7 && lane < 7 + T);
   for (int it = 0; it < iters; ++it) {
-    if (lane < kStride) S.geno[lane] = gene;
+    if (lane < kStride) S.geno[lane] = (double)gene;
     __syncthreads();
     const double E = evaluate<CAP, true>(C, LL, S, lane, nullptr, nullptr);
     const double gd = dof ? S.grad[lane] : 0.0;
@@ -492,25 +537,36 @@ __device__ void adadelta_wave(const EvalConst &C, const LaneLig<CAP> &LL, EvalLd
       best_E = E;
       best_gene = gene;
     }
-    Eg2 = rho * Eg2 + (1.0 - rho) * gd * gd;
-    const double dx = dof ? -sqrt(Edx2 + eps) / sqrt(Eg2 + eps) * gd : 0.0;
-    Edx2 = rho * Edx2 + (1.0 - rho) * dx * dx;
-    // orientation: q <- exp(dw/2) (x) q using the three rotation lanes
-    const double w0 = __shfl(dx, 3), w1 = __shfl(dx, 4), w2 = __shfl(dx, 5);
-    Q4 qc = {__shfl(gene, 3), __shfl(gene, 4), __shfl(gene, 5), __shfl(gene, 6)};
-    Q4 qn = apply_rotvec(qc, w0, w1, w2);
+    Eg2 = rho_d * Eg2 + (1.0 - rho_d) * gd * gd;
+    const float rg = fast_rsq((float)(Eg2 + eps_d));
+    const float dx = dof ? -__builtin_sqrtf(Edx2 + eps) * rg * (float)gd : 0.0f;
+    Edx2 = rho * Edx2 + (1.0f - rho) * dx * dx;
+    // orientation: q <- exp(dw/2) (x) q from the three rotation lanes
+    const float w0 = lane_f32(dx, 3), w1 = lane_f32(dx, 4), w2 = lane_f32(dx, 5);
+    const float qw = lane_f32(gene, 3), qx = lane_f32(gene, 4), qy = lane_f32(gene, 5), qz = lane_f32(gene, 6);
+    const float th = __builtin_sqrtf(w0 * w0 + w1 * w1 + w2 * w2);
+    float sh, ch;
+    __sincosf(0.5f * th, &sh, &ch);
+    const float f = th > 1e-30f ? sh / th : 0.5f;
+    const float rx = f * w0, ry = f * w1, rz = f * w2;
+    float nw = ch * qw - rx * qx - ry * qy - rz * qz;
+    float nx = ch * qx + rx * qw + ry * qz - rz * qy;
+    float ny = ch * qy - rx * qz + ry * qw + rz * qx;
+    float nz = ch * qz + rx * qy - ry * qx + rz * qw;
+    const float inv = fast_rsq(nw * nw + nx * nx + ny * ny + nz * nz);
     if (lane < 3) gene += dx;
-    else if (lane == 3) gene = qn.w;
-    else if (lane == 4) gene = qn.x;
-    else if (lane == 5) gene = qn.y;
-    else if (lane == 6) gene = qn.z;
-    else if (lane < 7 + T) gene = wrap_angle(gene + dx);
-    // genotypes stay FP32-representable: the stored best pose is exactly the
-    // evaluated one
-    gene = (double)(float)gene;
+    else if (lane == 3) gene = nw * inv;
+    else if (lane == 4) gene = nx * inv;
+    else if (lane == 5) gene = ny * inv;
+    else if (lane == 6) gene = nz * inv;
+    else if (lane < 7 + T) {
+      float th2 = gene + dx;
+      th2 -= 6.2831853071795865f * floorf((th2 + 3.14159265358979f) * 0.15915494309189535f);
+      gene = th2;
+    }
     __syncthreads();
   }
-  if (lane < kStride) geno_io[lane] = (float)best_gene;
+  if (lane < kStride) geno_io[lane] = best_gene;
   if (lane == 0) *E_io = (float)best_E;
 }
 
