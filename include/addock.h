@@ -102,7 +102,9 @@ typedef struct {
  * creates (hip_stream == NULL) or borrows (e.g. PyTorch's current stream)
  * the stream all work is queued on.  No GPU -> AD_E_DEVICE; malformed force
  * field -> AD_E_INVALID.  Device memory is owned by the context and freed by
- * ad_destroy (which first waits for the stream). */
+ * ad_destroy (which first waits for the stream).  Batches (ad_load_ligands)
+ * and pre-screens (ad_prescreen_create) refer to their context: free them
+ * before the context; using or freeing one after ad_destroy is undefined. */
 int ad_create(ad_ctx **out, int device, const ad_forcefield *ff, void *hip_stream);
 void ad_destroy(ad_ctx *ctx);
 const char *ad_last_error(const ad_ctx *ctx);
@@ -240,6 +242,67 @@ typedef struct {
 } ad_kernel_times;
 int ad_set_kernel_timing(ad_ctx *ctx, int enable);
 int ad_get_kernel_timing(ad_ctx *ctx, ad_kernel_times *out, int reset);
+
+
+/* ---- learned pre-screen ---------------------------------------------------
+ * In the screening setting (many ligands against one receptor, Sec. 1 and
+ * Sec. 2.2) a learned model ranks the ligands by predicted docking score so
+ * that full docking runs only on the best-ranked share.  The model reads the
+ * ligand graph only (no pose): atom features (32 per atom: one-hot type
+ * 0..15, charge, |charge|, one-hot degree 0,1,2,3,>=4, rotatable bonds at the
+ * atom / 2, constant 1 at index 31), 3 message-passing layers of width 128
+ *   H0 = r(relu(X W0 + b0)),  M = r(A H),  H' = r(relu([H | M] W_l + b_l))
+ * (A = bond adjacency), sum pooling g = r(sum H3) and an MLP
+ *   z1 = r(relu(g U1 + c1)), z2 = r(relu(z1 U2 + c2)), p = z2 U3 + c3
+ * with 256-wide hidden layers.  r() rounds to bfloat16 (nearest even): GEMM
+ * operands are BF16, accumulation FP32 (gfx950 MFMA).  Training minimises
+ *   mean (p - y)^2 + lam * mean over pairs y_i < y_j of softplus((p_i - p_j)/tau)
+ * on standardised labels y with Adam on FP32 master weights.
+ *
+ * Parameters are one float vector of ad_prescreen_n_params() entries:
+ * W0[32][128], b0[128], then for l = 1..3 W_l[256][128] (rows 0..127 act on
+ * H, 128..255 on M), b_l[128], then U1[128][256], c1[256], U2[256][256],
+ * c2[256], U3[256], c3[1]; all matrices row-major [in][out].
+ * Ligands must have atoms with at most 8 bonds (AD_E_INVALID otherwise). */
+typedef struct ad_prescreen ad_prescreen;
+typedef struct {
+  int batch_size;        /* minibatch size for training, 2..4096 (256) */
+  double lr;             /* Adam step (1e-3) */
+  double lam, tau;       /* ranking-loss weight (1.0) and temperature (0.5) */
+  double beta1, beta2;   /* Adam moments (0.9, 0.999) */
+  double eps;            /* Adam epsilon (1e-8) */
+  double label_max;      /* labels above are clipped to it before use (HUGE_VAL: none);
+                            docking energies of ligands that do not fit are large and
+                            positive, and only the low end is ranked */
+} ad_prescreen_cfg;
+
+int ad_prescreen_n_params(void);
+/* cfg may be null (defaults above).  Weights He-uniform from `seed` (the
+ * output layer U3 scaled by 1/100), biases zero.  The model lives on the
+ * context's device and uses its stream. */
+int ad_prescreen_create(ad_ctx *ctx, const ad_prescreen_cfg *cfg, uint64_t seed, ad_prescreen **out);
+void ad_prescreen_destroy(ad_prescreen *ps);
+/* host float [n_params]; set_params also clears the Adam moments and step */
+int ad_prescreen_set_params(ad_prescreen *ps, const float *params);
+int ad_prescreen_get_params(ad_prescreen *ps, float *params);
+/* label scale: predictions are mean + sd * p (set by ad_prescreen_train) */
+int ad_prescreen_set_scale(ad_prescreen *ps, double mean, double sd);
+int ad_prescreen_get_scale(ad_prescreen *ps, double *mean, double *sd);
+/* Predicted score of ligands lig_idx[0..n) of batch b (lig_idx null: 0..n-1)
+ * into scores (host, [n]).  Synchronous. */
+int ad_prescreen_predict(ad_prescreen *ps, const ad_batch *b, int n, const int *lig_idx, float *scores);
+/* One minibatch (2 <= n <= 4096): forward, loss on labels clipped to
+ * label_max and standardised with the current scale, backward.  Outputs (host, each optional): loss, grad
+ * [n_params] and the standardised predictions pred_std [n].  No update. */
+int ad_prescreen_grad(ad_prescreen *ps, const ad_batch *b, int n, const int *lig_idx, const float *labels,
+                      float *loss, float *grad, float *pred_std);
+/* Trains for `epochs` passes over n labelled ligands: clips the labels to
+ * label_max, sets the scale to their mean and standard deviation, shuffles with `seed` each epoch and
+ * takes one Adam step per full minibatch (a tail shorter than batch_size is
+ * skipped).  loss_curve (optional, host [epochs]) receives each epoch's mean
+ * minibatch loss.  Synchronous. */
+int ad_prescreen_train(ad_prescreen *ps, const ad_batch *b, int n, const int *lig_idx, const float *labels,
+                       int epochs, uint64_t seed, float *loss_curve);
 
 #ifdef __cplusplus
 }

@@ -10,13 +10,14 @@ from __future__ import annotations
 import ctypes as C
 import os
 import subprocess
+import weakref
 
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB_PATH = os.path.join(HERE, "libaddock.so")
-SOURCES = ["csrc/prep.cpp", "csrc/api.cpp", "csrc/dock.cpp", "csrc/kernels.hip"]
+SOURCES = ["csrc/prep.cpp", "csrc/api.cpp", "csrc/dock.cpp", "csrc/kernels.hip", "csrc/prescreen.hip"]
 
 AD_OK, AD_E_INVALID, AD_E_NOMAP, AD_E_OOM, AD_E_DEVICE, AD_E_STATE, AD_E_UNSUPPORTED, AD_E_HIP = 0, -1, -2, -3, -4, -5, -6, -7
 ERR_NAMES = {0: "AD_OK", -1: "AD_E_INVALID", -2: "AD_E_NOMAP", -3: "AD_E_OOM", -4: "AD_E_DEVICE",
@@ -26,7 +27,9 @@ MAX_TYPES, STRIDE = 16, 40
 EXPORTS = ["ad_create", "ad_destroy", "ad_last_error", "ad_set_stream", "ad_synchronize", "ad_load_grids",
            "ad_build_grids", "ad_ligand_check", "ad_load_ligands", "ad_free_batch", "ad_batch_info",
            "ad_score_poses", "ad_dock_batch", "ad_local_search", "ad_initial_population",
-           "ad_set_kernel_timing", "ad_get_kernel_timing"]
+           "ad_set_kernel_timing", "ad_get_kernel_timing", "ad_prescreen_n_params", "ad_prescreen_create",
+           "ad_prescreen_destroy", "ad_prescreen_set_params", "ad_prescreen_get_params", "ad_prescreen_set_scale",
+           "ad_prescreen_get_scale", "ad_prescreen_predict", "ad_prescreen_grad", "ad_prescreen_train"]
 
 
 def build(verbose: bool = False, arch: str = "gfx950") -> str:
@@ -85,6 +88,15 @@ class KernelTimes(C.Structure):
 KERNEL_KINDS = ("init", "ga", "ls", "score")
 
 
+class PrescreenCfg(C.Structure):
+    _fields_ = [("batch_size", C.c_int), ("lr", C.c_double), ("lam", C.c_double), ("tau", C.c_double),
+                ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double), ("label_max", C.c_double)]
+
+
+DEFAULT_PRESCREEN = dict(batch_size=256, lr=1e-3, lam=1.0, tau=0.5, beta1=0.9, beta2=0.999, eps=1e-8,
+                         label_max=float("inf"))
+
+
 class DockResult(C.Structure):
     _fields_ = [("best_energy", C.c_float), ("best_score", C.c_float),
                 ("best_genotype", C.c_float * STRIDE), ("best_run", C.c_int),
@@ -132,6 +144,17 @@ def lib():
     L.ad_dock_batch.argtypes = [vp, vp, C.POINTER(DockParams), C.c_uint64, vp, C.POINTER(DockResult), fp, fp]
     L.ad_local_search.argtypes = [vp, vp, C.c_int, vp, vp, vp, C.POINTER(DockParams), C.c_int, C.c_int]
     L.ad_initial_population.argtypes = [vp, vp, C.c_int, C.c_uint32, C.c_int, C.c_int, C.c_uint64, fp]
+    L.ad_prescreen_n_params.argtypes = []
+    L.ad_prescreen_create.argtypes = [vp, C.POINTER(PrescreenCfg), C.c_uint64, C.POINTER(vp)]
+    L.ad_prescreen_destroy.argtypes = [vp]
+    L.ad_prescreen_destroy.restype = None
+    L.ad_prescreen_set_params.argtypes = [vp, fp]
+    L.ad_prescreen_get_params.argtypes = [vp, fp]
+    L.ad_prescreen_set_scale.argtypes = [vp, C.c_double, C.c_double]
+    L.ad_prescreen_get_scale.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    L.ad_prescreen_predict.argtypes = [vp, vp, C.c_int, vp, fp]
+    L.ad_prescreen_grad.argtypes = [vp, vp, C.c_int, vp, fp, fp, fp, fp]
+    L.ad_prescreen_train.argtypes = [vp, vp, C.c_int, vp, fp, C.c_int, C.c_uint64, fp]
     _lib = L
     return L
 
@@ -223,6 +246,7 @@ class Batch:
         self.ctx = ctx
         self.h = handle
         self.n = n
+        ctx._children.add(self)
 
     def info(self, i):
         a, t, p, f, d = C.c_int(), C.c_int(), C.c_int(), C.c_int(), C.c_int()
@@ -255,6 +279,7 @@ class Context:
         if stream == "torch":
             import torch
             stream = torch.cuda.current_stream(device).cuda_stream
+        self._children = weakref.WeakSet()   # batches and pre-screens: freed before the context
         rc = L.ad_create(C.byref(h), device, C.byref(self.ff), C.c_void_p(stream) if stream else None)
         if rc:
             raise AddockError(rc, "ad_create failed")
@@ -375,7 +400,86 @@ class Context:
 
     def close(self):
         if getattr(self, "h", None):
+            for child in list(self._children):
+                child.close() if isinstance(child, Prescreen) else child.free()
             lib().ad_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _fptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_float)) if a is not None else None
+
+
+class Prescreen:
+    """The learned pre-screen (ad_prescreen_*) on a context's device."""
+
+    def __init__(self, ctx: Context, seed: int = 0, **cfg):
+        d = dict(DEFAULT_PRESCREEN)
+        d.update(cfg)
+        c = PrescreenCfg()
+        for k, v in d.items():
+            setattr(c, k, v)
+        self.ctx = ctx
+        h = C.c_void_p()
+        ctx._check(lib().ad_prescreen_create(ctx.h, C.byref(c), seed, C.byref(h)))
+        self.h = h
+        ctx._children.add(self)
+        self.n_params = lib().ad_prescreen_n_params()
+
+    def ad_prescreen_set_params(self, params):
+        p = _np(params, np.float32)
+        assert p.size == self.n_params
+        self.ctx._check(lib().ad_prescreen_set_params(self.h, _fptr(p)))
+
+    def ad_prescreen_get_params(self):
+        p = np.empty(self.n_params, np.float32)
+        self.ctx._check(lib().ad_prescreen_get_params(self.h, _fptr(p)))
+        return p
+
+    def ad_prescreen_set_scale(self, mean, sd):
+        self.ctx._check(lib().ad_prescreen_set_scale(self.h, float(mean), float(sd)))
+
+    def ad_prescreen_get_scale(self):
+        m, s = C.c_double(), C.c_double()
+        self.ctx._check(lib().ad_prescreen_get_scale(self.h, C.byref(m), C.byref(s)))
+        return m.value, s.value
+
+    def ad_prescreen_predict(self, batch, lig_idx=None):
+        idx = _np(lig_idx, np.int32) if lig_idx is not None else None
+        n = len(idx) if idx is not None else batch.n
+        out = np.empty(n, np.float32)
+        self.ctx._check(lib().ad_prescreen_predict(self.h, batch.h, n, _ptr(idx), _fptr(out)))
+        return out
+
+    def ad_prescreen_grad(self, batch, lig_idx, labels):
+        idx = _np(lig_idx, np.int32)
+        y = _np(labels, np.float32)
+        n = len(idx)
+        loss = np.zeros(1, np.float32)
+        grad = np.empty(self.n_params, np.float32)
+        pred = np.empty(n, np.float32)
+        self.ctx._check(lib().ad_prescreen_grad(self.h, batch.h, n, _ptr(idx), _fptr(y), _fptr(loss), _fptr(grad),
+                                                _fptr(pred)))
+        return float(loss[0]), grad, pred
+
+    def ad_prescreen_train(self, batch, lig_idx, labels, epochs, seed=0):
+        idx = _np(lig_idx, np.int32) if lig_idx is not None else None
+        y = _np(labels, np.float32)
+        n = len(y)
+        curve = np.zeros(max(1, epochs), np.float32)
+        self.ctx._check(lib().ad_prescreen_train(self.h, batch.h, n, _ptr(idx), _fptr(y), epochs, seed,
+                                                 _fptr(curve)))
+        return curve[:epochs]
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ad_prescreen_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -14,6 +14,8 @@ constexpr int kMaxAtoms = AD_MAX_ATOMS;
 constexpr int kMaxTor = AD_MAX_TORSIONS;
 constexpr int kStride = AD_GENO_STRIDE;
 constexpr int kMaxTypes = AD_MAX_TYPES;
+constexpr int kFeat = 32;     // pre-screen atom features
+constexpr int kMaxDeg = 8;    // pre-screen neighbour slots per atom
 
 // Per-ligand descriptor in device memory.
 struct LigDesc {
@@ -115,5 +117,8 @@ int prepare_ligand(const ad_ligand &L, const ad_forcefield &ff, const int *type_
                    std::string *err);
 void build_lj_table(const ad_forcefield &ff, std::vector<LJRec> *out);
 FFConst make_ffconst(const ad_forcefield &ff);
+uint16_t f32_to_bf16(float f);
+bool featurize(const ad_ligand &L, const std::vector<int> &perm, std::vector<uint16_t> *X,
+               std::vector<uint8_t> *nbr);
 
 }  // namespace ad

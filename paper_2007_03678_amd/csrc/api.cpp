@@ -376,7 +376,23 @@ extern "C" int ad_load_ligands(ad_ctx *c, int n, const ad_ligand *ligs, ad_batch
     if (bytes && hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice) != hipSuccess) return false;
     return true;
   };
-  bool ok = up((void **)&b->lig, lig.data(), lig.size() * sizeof(LigDesc)) &&
+  std::vector<uint16_t> psx;
+  std::vector<uint8_t> psn;
+  for (int i = 0; i < n; ++i) {
+    std::vector<uint16_t> x1;
+    std::vector<uint8_t> n1;
+    if (!featurize(ligs[i], prep[i].perm, &x1, &n1)) {
+      b->ps_ok = false;
+      x1.assign((size_t)prep[i].n_atoms * kFeat, 0);
+      n1.assign((size_t)prep[i].n_atoms * kMaxDeg, 0xff);
+    }
+    psx.insert(psx.end(), x1.begin(), x1.end());
+    psn.insert(psn.end(), n1.begin(), n1.end());
+  }
+  b->n_atoms_total = (int)geo.size();
+  bool ok = up((void **)&b->ps_x, psx.data(), psx.size() * sizeof(uint16_t)) &&
+            up((void **)&b->ps_nbr, psn.data(), psn.size()) &&
+            up((void **)&b->lig, lig.data(), lig.size() * sizeof(LigDesc)) &&
             up((void **)&b->geo, geo.data(), geo.size() * sizeof(AtomGeo)) &&
             up((void **)&b->info, info.data(), info.size() * sizeof(AtomInfo)) &&
             up((void **)&b->pairs, pairs.data(), pairs.size() * sizeof(PairRec)) &&
@@ -398,6 +414,8 @@ extern "C" void ad_free_batch(ad_batch *b) {
   hipFree(b->info);
   hipFree(b->pairs);
   hipFree(b->tors);
+  hipFree(b->ps_x);
+  hipFree(b->ps_nbr);
   delete b;
 }
 

@@ -70,6 +70,12 @@ struct ad_batch {
   ad::TorRec *tors = nullptr;
   std::vector<ad::LigDesc> lig_host;
   std::vector<int> depth_sum;
+  // pre-screen inputs (internal atom order): BF16 features [atoms][32] and
+  // neighbour slots [atoms][8]; ps_ok = every atom has <= 8 neighbours
+  uint16_t *ps_x = nullptr;
+  uint8_t *ps_nbr = nullptr;
+  bool ps_ok = true;
+  int n_atoms_total = 0;
   int map_of_type[AD_MAX_TYPES];   // map index of each type used by the batch at load time (-1: unused)
 };
 

@@ -12,6 +12,7 @@
 //     >= 4 (1-2, 1-3, 1-4 excluded).
 #include <math.h>
 #include <stdio.h>
+#include <string.h>
 
 #include <algorithm>
 #include <cmath>
@@ -279,6 +280,55 @@ FFConst make_ffconst(const ad_forcefield &ff) {
   c.n_types = ff.n_types;
   c.k_out = ff.k_out;
   return c;
+}
+
+}  // namespace ad
+
+namespace ad {
+
+uint16_t f32_to_bf16(float f) {
+  uint32_t u;
+  memcpy(&u, &f, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// Pre-screen inputs of one ligand in the internal atom order: 32 features
+// per atom (one-hot type, q, |q|, one-hot degree 0..3 / >=4, rotatable bonds
+// at the atom / 2, constant 1), rounded to BF16, and up to kMaxDeg neighbour
+// indices per atom (0xff = none).  Returns false if an atom has more
+// neighbours than that.
+bool featurize(const ad_ligand &L, const std::vector<int> &perm, std::vector<uint16_t> *X,
+               std::vector<uint8_t> *nbr) {
+  const int n = L.n_atoms;
+  std::vector<int> pos(n);
+  for (int s = 0; s < n; ++s) pos[perm[s]] = s;
+  std::vector<int> deg(n, 0), rot(n, 0);
+  nbr->assign((size_t)n * kMaxDeg, 0xff);
+  for (int b = 0; b < L.n_bonds; ++b) {
+    const int u = L.bonds[2 * b], v = L.bonds[2 * b + 1];
+    if (deg[u] >= kMaxDeg || deg[v] >= kMaxDeg) return false;
+    (*nbr)[(size_t)pos[u] * kMaxDeg + deg[u]] = (uint8_t)pos[v];
+    (*nbr)[(size_t)pos[v] * kMaxDeg + deg[v]] = (uint8_t)pos[u];
+    ++deg[u];
+    ++deg[v];
+    if (L.rotatable[b]) {
+      ++rot[u];
+      ++rot[v];
+    }
+  }
+  X->assign((size_t)n * kFeat, 0);
+  for (int s = 0; s < n; ++s) {
+    const int i = perm[s];
+    uint16_t *x = &(*X)[(size_t)s * kFeat];
+    x[L.type_id[i]] = f32_to_bf16(1.0f);
+    x[16] = f32_to_bf16(L.charge[i]);
+    x[17] = f32_to_bf16(std::fabs(L.charge[i]));
+    x[18 + std::min(deg[i], 4)] = f32_to_bf16(1.0f);
+    x[23] = f32_to_bf16(0.5f * rot[i]);
+    x[31] = f32_to_bf16(1.0f);
+  }
+  return true;
 }
 
 }  // namespace ad

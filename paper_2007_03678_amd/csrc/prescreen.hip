@@ -1,0 +1,918 @@
+// Learned pre-screen on the GPU: message passing over the ligand graph,
+// sum pooling and an MLP predict each ligand's docking score, so that full
+// docking can be spent on the ligands ranked best (the screening setting of
+// Sec. 1 / Sec. 2.2: many ligands against one receptor).
+//
+// Network (BF16 operands, FP32 accumulation; r() = round to BF16):
+//   H0 = r(relu(X W0 + b0)); for l = 1..3: M = r(A H), H = r(relu([H|M] W_l + b_l))
+//   g = r(sum_atoms H3); z1 = r(relu(g U1 + c1)); z2 = r(relu(z1 U2 + c2)); p = z2 U3 + c3
+// Loss: mean (p - y)^2 + lam * mean over (y_i < y_j) of softplus((p_i - p_j)/tau),
+// labels standardised; Adam on FP32 master weights, BF16 mirror for the GEMMs.
+//
+// GEMMs run on the gfx950 MFMA unit (v_mfma_f32_32x32x16_bf16): 64x64 output
+// tiles per 256-thread work-group (2x2 wavefronts of 32x32), K in steps of
+// 32 through LDS.  Weight gradients reduce over graph nodes in split-K
+// chunks written to a partial buffer and summed in a fixed order, so every
+// result is deterministic.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+#include <random>
+#include <string>
+#include <vector>
+
+#include "api_internal.h"
+
+namespace ad {
+namespace {
+
+constexpr int kW = 128;     // message-passing width
+constexpr int kH = 256;     // MLP width
+constexpr int kLayers = 3;
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// ---------------------------------------------------------------------------
+// GEMM  C[M x N] = A[M x K] . B[K x N]
+// A modes: 0 row-major A1[m*lda1 + k] (rows optionally through a_rows),
+//          1 two row-major sources side by side (k < split from A1),
+//          2 column access A1[k*lda1 + m] (a transposed operand),
+//          3 column access of two sources (m < split from A1).
+// B modes: 0 B[k*ldb + n], 1 B[n*ldb + k] (a transposed operand).
+// ---------------------------------------------------------------------------
+struct GemmArgs {
+  int M, N, K;
+  int a_mode, split;
+  const uint16_t *A1, *A2;
+  int lda1, lda2;
+  const int *a_rows;
+  int b_mode;
+  const uint16_t *B;
+  int ldb;
+  const float *bias;
+  int relu;
+  const uint16_t *mask;   // zero where mask[m*ldm + n] <= 0
+  int ldm;
+  float *C32;
+  int ldc32;
+  uint16_t *C16;
+  int ldc16;
+  float *part;            // split-K partials [gridDim.z][M][N]
+  int k_chunk;
+};
+
+constexpr int BM = 64, BN = 64, BK = 32, BKP = BK + 8;
+
+__device__ __forceinline__ uint16_t gemm_a(const GemmArgs &g, int m, int k) {
+  switch (g.a_mode) {
+    case 0: {
+      const int r = g.a_rows ? g.a_rows[m] : m;
+      return g.A1[(size_t)r * g.lda1 + k];
+    }
+    case 1:
+      return k < g.split ? g.A1[(size_t)m * g.lda1 + k] : g.A2[(size_t)m * g.lda2 + (k - g.split)];
+    case 2:
+      return g.A1[(size_t)k * g.lda1 + m];
+    default:
+      return m < g.split ? g.A1[(size_t)k * g.lda1 + m] : g.A2[(size_t)k * g.lda2 + (m - g.split)];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
+  __shared__ __attribute__((aligned(16))) uint16_t As[BM][BKP];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[BN][BKP];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int kz0 = blockIdx.z * g.k_chunk, kz1 = min(g.K, kz0 + g.k_chunk);
+  const bool a_rowwise = g.a_mode <= 1;
+  f32x16 acc;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
+  for (int k0 = kz0; k0 < kz1; k0 += BK) {
+    for (int e = tid; e < BM * BK; e += 256) {
+      const int r = a_rowwise ? e / BK : e % BM;
+      const int kk = a_rowwise ? e % BK : e / BM;
+      const int m = m0 + r, k = k0 + kk;
+      As[r][kk] = (m < g.M && k < kz1) ? gemm_a(g, m, k) : (uint16_t)0;
+    }
+    for (int e = tid; e < BN * BK; e += 256) {
+      const int nn = g.b_mode == 0 ? e % BN : e / BK;
+      const int kk = g.b_mode == 0 ? e / BN : e % BK;
+      const int n = n0 + nn, k = k0 + kk;
+      uint16_t v = 0;
+      if (n < g.N && k < kz1) v = g.b_mode == 0 ? g.B[(size_t)k * g.ldb + n] : g.B[(size_t)n * g.ldb + k];
+      Bs[nn][kk] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < BK; s += 16) {
+      const int kk = s + (lane >> 5) * 8;
+      const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&As[wm * 32 + (lane & 31)][kk]);
+      const bf16x8 b = *reinterpret_cast<const bf16x8 *>(&Bs[wn * 32 + (lane & 31)][kk]);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int row = m0 + wm * 32 + (i >> 2) * 8 + (lane >> 5) * 4 + (i & 3);
+    const int col = n0 + wn * 32 + (lane & 31);
+    if (row >= g.M || col >= g.N) continue;
+    float v = acc[i];
+    if (g.part) {
+      g.part[((size_t)blockIdx.z * g.M + row) * g.N + col] = v;
+      continue;
+    }
+    if (g.bias) v += g.bias[col];
+    if (g.relu) v = fmaxf(v, 0.0f);
+    if (g.mask && !(bf2f(g.mask[(size_t)row * g.ldm + col]) > 0.0f)) v = 0.0f;
+    if (g.C32) g.C32[(size_t)row * g.ldc32 + col] = v;
+    if (g.C16) g.C16[(size_t)row * g.ldc16 + col] = f2bf(v);
+  }
+}
+
+// sum of split-K partials in chunk order
+__global__ void k_reduce_parts(const float *part, int Z, size_t MN, float *out) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= MN) return;
+  float s = 0.0f;
+  for (int z = 0; z < Z; ++z) s += part[(size_t)z * MN + i];
+  out[i] = s;
+}
+
+// ---------------------------------------------------------------------------
+// graph kernels (minibatch node layout: the nodes of graph b are
+// [gstart[b], gstart[b+1]); node m is atom node_atom[m] of the batch)
+// ---------------------------------------------------------------------------
+struct GraphArgs {
+  const int *node_atom;   // [Nn] batch atom index
+  const int *node_g0;     // [Nn] first node of the node's graph
+  const int *node_graph;  // [Nn] graph of the node
+  const int *gstart;      // [B+1]
+  const uint8_t *nbr;     // batch [atoms][8] local neighbour indices
+  int Nn, B;
+};
+
+// rows of the batch features for the minibatch nodes
+__global__ void k_gather_x(GraphArgs G, const uint16_t *X, uint16_t *Xmb) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)G.Nn * kFeat) return;
+  const int m = (int)(i / kFeat), c = (int)(i % kFeat);
+  Xmb[i] = X[(size_t)G.node_atom[m] * kFeat + c];
+}
+
+// M[m] = r(sum over bonded neighbours of H); at most 8 BF16 terms, summed in FP32
+__global__ void k_neighbour_sum(GraphArgs G, const uint16_t *H, uint16_t *M) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)G.Nn * kW) return;
+  const int m = (int)(i / kW), c = (int)(i % kW);
+  const uint8_t *nb = G.nbr + (size_t)G.node_atom[m] * kMaxDeg;
+  float s = 0.0f;
+  for (int d = 0; d < kMaxDeg && nb[d] != 0xff; ++d) s += bf2f(H[(size_t)(G.node_g0[m] + nb[d]) * kW + c]);
+  M[i] = f2bf(s);
+}
+
+// dP_prev[m] = [H_prev > 0] * r(dHM[m, :128] + sum over neighbours of dHM[., 128:])
+__global__ void k_neighbour_bwd(GraphArgs G, const uint16_t *dHM, const uint16_t *Hprev, uint16_t *dP) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)G.Nn * kW) return;
+  const int m = (int)(i / kW), c = (int)(i % kW);
+  const uint8_t *nb = G.nbr + (size_t)G.node_atom[m] * kMaxDeg;
+  float s = bf2f(dHM[(size_t)m * 2 * kW + c]);
+  for (int d = 0; d < kMaxDeg && nb[d] != 0xff; ++d)
+    s += bf2f(dHM[(size_t)(G.node_g0[m] + nb[d]) * 2 * kW + kW + c]);
+  dP[i] = bf2f(Hprev[i]) > 0.0f ? f2bf(s) : (uint16_t)0;
+}
+
+// g[b] = r(sum of H over the graph's nodes).  The sum of up to 128 BF16
+// values is exact in FP64, so its rounding (FP64 -> FP32 -> BF16) does not
+// depend on the summation order.
+__global__ void k_pool(GraphArgs G, const uint16_t *H, uint16_t *gp) {
+  const int b = blockIdx.x, c = threadIdx.x;
+  double s = 0.0;
+  for (int m = G.gstart[b]; m < G.gstart[b + 1]; ++m) s += (double)bf2f(H[(size_t)m * kW + c]);
+  gp[(size_t)b * kW + c] = f2bf((float)s);
+}
+
+// dP3[m] = [H3 > 0] * dg[graph(m)]
+__global__ void k_pool_bwd(GraphArgs G, const uint16_t *dg, const uint16_t *H, uint16_t *dP) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)G.Nn * kW) return;
+  const int m = (int)(i / kW), c = (int)(i % kW);
+  dP[i] = bf2f(H[i]) > 0.0f ? dg[(size_t)G.node_graph[m] * kW + c] : (uint16_t)0;
+}
+
+// p[b] = z2[b] . U3 + c3 (FP32, j ascending): one wavefront per graph
+__global__ void k_head(const uint16_t *z2, const uint16_t *U3, const float *c3, int B, float *p) {
+  const int b = blockIdx.x, lane = threadIdx.x;
+  if (b >= B) return;
+  float s = 0.0f;
+  for (int j = lane; j < kH; j += 64) s += bf2f(z2[(size_t)b * kH + j]) * bf2f(U3[j]);
+  for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
+  if (lane == 0) p[b] = s + c3[0];
+}
+
+// loss and dL/dp over one minibatch (single work-group, fixed-order sums)
+__global__ __launch_bounds__(256) void k_loss(const float *p, const float *y, int B, float lam, float tau,
+                                              float *loss_out, float *dp) {
+  __shared__ float red[256];
+  __shared__ float npairs_s;
+  const int t = threadIdx.x;
+  float cnt = 0.0f;
+  for (int i = t; i < B; i += 256)
+    for (int j = 0; j < B; ++j) cnt += y[i] < y[j] ? 1.0f : 0.0f;
+  red[t] = cnt;
+  __syncthreads();
+  if (t == 0) {
+    float s = 0.0f;
+    for (int k = 0; k < 256; ++k) s += red[k];
+    npairs_s = s;
+  }
+  __syncthreads();
+  const float np = npairs_s;
+  const float wr = (np > 0.0f && lam != 0.0f) ? lam / np : 0.0f;
+  float lsum = 0.0f;
+  for (int i = t; i < B; i += 256) {
+    const float d = p[i] - y[i];
+    float gi = 2.0f * d / B;
+    float li = d * d / B;
+    if (wr != 0.0f) {
+      for (int j = 0; j < B; ++j) {
+        if (y[i] < y[j]) {
+          const float z = (p[i] - p[j]) / tau;
+          li += wr * (fmaxf(z, 0.0f) + log1pf(expf(-fabsf(z))));
+          gi += wr / tau / (1.0f + expf(-z));
+        }
+        if (y[j] < y[i]) {
+          const float z = (p[j] - p[i]) / tau;
+          gi -= wr / tau / (1.0f + expf(-z));
+        }
+      }
+    }
+    dp[i] = gi;
+    lsum += li;
+  }
+  red[t] = lsum;
+  __syncthreads();
+  if (t == 0) {
+    float s = 0.0f;
+    for (int k = 0; k < 256; ++k) s += red[k];
+    *loss_out = s;
+  }
+}
+
+// head backward: dz2 = [z2 > 0] r(dp U3); dU3 = z2^T dp; dc3 = sum dp
+__global__ void k_head_bwd(const uint16_t *z2, const uint16_t *U3, const float *dp, int B, uint16_t *dz2, float *dU3,
+                           float *dc3) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < kH) {
+    float s = 0.0f;
+    for (int b = 0; b < B; ++b) {
+      const float z = bf2f(z2[(size_t)b * kH + j]);
+      s += z * dp[b];
+      dz2[(size_t)b * kH + j] = z > 0.0f ? f2bf(dp[b] * bf2f(U3[j])) : (uint16_t)0;
+    }
+    dU3[j] = s;
+  }
+  if (j == 0) {
+    float s = 0.0f;
+    for (int b = 0; b < B; ++b) s += dp[b];
+    dc3[0] = s;
+  }
+}
+
+// column sums (bias gradients), rows in order
+__global__ void k_colsum(const uint16_t *X, int R, int Cn, float *out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= Cn) return;
+  float s = 0.0f;
+  for (int r = 0; r < R; ++r) s += bf2f(X[(size_t)r * Cn + c]);
+  out[c] = s;
+}
+
+__global__ void k_adam(float *w, const float *gr, float *m, float *v, size_t n, float lr, float b1, float b2,
+                       float eps, float c1, float c2, uint16_t *wbf) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float g = gr[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * g;
+  const float vi = b2 * v[i] + (1.0f - b2) * g * g;
+  m[i] = mi;
+  v[i] = vi;
+  const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  w[i] = wi;
+  wbf[i] = f2bf(wi);
+}
+
+__global__ void k_cast(const float *w, size_t n, uint16_t *wbf) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) wbf[i] = f2bf(w[i]);
+}
+
+// standardised prediction -> label scale
+__global__ void k_unscale(const float *p, int n, float mean, float sd, float *out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = mean + sd * p[i];
+}
+
+
+inline unsigned nblk(size_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+}  // namespace ad
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+using namespace ad;
+
+namespace {
+
+struct Offs {
+  size_t W[kLayers + 1], b[kLayers + 1], U1, c1, U2, c2, U3, c3, total;
+};
+
+Offs make_offs() {
+  Offs o;
+  size_t p = 0;
+  o.W[0] = p;
+  p += (size_t)kFeat * kW;
+  o.b[0] = p;
+  p += kW;
+  for (int l = 1; l <= kLayers; ++l) {
+    o.W[l] = p;
+    p += (size_t)2 * kW * kW;
+    o.b[l] = p;
+    p += kW;
+  }
+  o.U1 = p;
+  p += (size_t)kW * kH;
+  o.c1 = p;
+  p += kH;
+  o.U2 = p;
+  p += (size_t)kH * kH;
+  o.c2 = p;
+  p += kH;
+  o.U3 = p;
+  p += kH;
+  o.c3 = p;
+  p += 1;
+  o.total = p;
+  return o;
+}
+
+}  // namespace
+
+struct ad_prescreen {
+  ad_ctx *ctx = nullptr;
+  Offs o;
+  ad_prescreen_cfg cfg;
+  float *w = nullptr, *gr = nullptr, *m = nullptr, *v = nullptr;
+  uint16_t *wbf = nullptr;
+  double mean = 0.0, sd = 1.0;
+  int64_t step = 0;
+  // grow-only work buffer
+  char *work = nullptr;
+  size_t work_bytes = 0;
+  std::vector<float> loss_log;
+};
+
+namespace {
+
+#define PS_TRY(ctx, expr)                                    \
+  do {                                                       \
+    hipError_t _e = (expr);                                  \
+    if (_e != hipSuccess) return (ctx)->hip_fail(_e, #expr); \
+  } while (0)
+
+size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// minibatch workspace
+struct MB {
+  int B = 0, Nn = 0;
+  int *node_atom, *node_g0, *node_graph, *gstart;
+  uint16_t *Xmb, *H[kLayers + 1], *M[kLayers + 1], *g, *z1, *z2, *dz1, *dz2, *dg, *dP, *dP2, *dHM;
+  float *p, *y, *dp, *loss, *part;
+  size_t part_floats;
+};
+
+constexpr int kSplitRows = 2048;   // nodes per split-K chunk of a weight gradient
+
+int setup_mb(ad_prescreen *ps, const ad_batch *b, const int *sel, int B, bool train, MB *mb) {
+  ad_ctx *c = ps->ctx;
+  std::vector<int> gstart(B + 1, 0);
+  for (int i = 0; i < B; ++i) gstart[i + 1] = gstart[i] + b->lig_host[sel[i]].n_atoms;
+  const int Nn = gstart[B];
+  std::vector<int> na(Nn), ng0(Nn), ngr(Nn);
+  for (int i = 0; i < B; ++i) {
+    const LigDesc &d = b->lig_host[sel[i]];
+    for (int a = 0; a < d.n_atoms; ++a) {
+      na[gstart[i] + a] = d.atom_off + a;
+      ng0[gstart[i] + a] = gstart[i];
+      ngr[gstart[i] + a] = i;
+    }
+  }
+  // split-K partials: the largest of the node-reduced [256 x 128] and the
+  // graph-reduced [256 x 256] weight gradients
+  const size_t z_nodes = std::max(1, (Nn + kSplitRows - 1) / kSplitRows);
+  const size_t z_graphs = std::max(1, (B + kSplitRows - 1) / kSplitRows);
+  const size_t part_floats = std::max(z_nodes * 2 * kW * kW, z_graphs * kH * kH);
+  size_t sz = 4 * al((size_t)Nn * 4) + al((size_t)(B + 1) * 4) + al((size_t)Nn * kFeat * 2);
+  const size_t hsz = al((size_t)Nn * kW * 2);
+  sz += (kLayers + 1) * hsz + kLayers * hsz;                         // H, M
+  sz += al((size_t)B * kW * 2) + 2 * al((size_t)B * kH * 2);         // g z1 z2
+  sz += 4 * al((size_t)B * 4) + al(4);                                // p y dp loss
+  if (train) {
+    sz += 2 * al((size_t)B * kH * 2) + al((size_t)B * kW * 2);       // dz1 dz2 dg
+    sz += 2 * hsz + al((size_t)Nn * 2 * kW * 2);                      // dP dP2 dHM
+    sz += al(part_floats * 4);
+  }
+  if (ps->work_bytes < sz) {
+    hipStreamSynchronize(c->stream);
+    if (ps->work) hipFree(ps->work);
+    ps->work = nullptr;
+    ps->work_bytes = 0;
+    if (hipMalloc(&ps->work, sz) != hipSuccess) return c->fail(AD_E_OOM, "cannot allocate pre-screen workspace");
+    ps->work_bytes = sz;
+  }
+  char *q = ps->work;
+  auto take = [&](size_t n) {
+    char *r = q;
+    q += al(n);
+    return r;
+  };
+  mb->B = B;
+  mb->Nn = Nn;
+  mb->node_atom = (int *)take((size_t)Nn * 4);
+  mb->node_g0 = (int *)take((size_t)Nn * 4);
+  mb->node_graph = (int *)take((size_t)Nn * 4);
+  take((size_t)Nn * 4);
+  mb->gstart = (int *)take((size_t)(B + 1) * 4);
+  mb->Xmb = (uint16_t *)take((size_t)Nn * kFeat * 2);
+  for (int l = 0; l <= kLayers; ++l) mb->H[l] = (uint16_t *)take((size_t)Nn * kW * 2);
+  mb->M[0] = nullptr;
+  for (int l = 1; l <= kLayers; ++l) mb->M[l] = (uint16_t *)take((size_t)Nn * kW * 2);
+  mb->g = (uint16_t *)take((size_t)B * kW * 2);
+  mb->z1 = (uint16_t *)take((size_t)B * kH * 2);
+  mb->z2 = (uint16_t *)take((size_t)B * kH * 2);
+  mb->p = (float *)take((size_t)B * 4);
+  mb->y = (float *)take((size_t)B * 4);
+  mb->dp = (float *)take((size_t)B * 4);
+  take((size_t)B * 4);
+  mb->loss = (float *)take(4);
+  if (train) {
+    mb->dz1 = (uint16_t *)take((size_t)B * kH * 2);
+    mb->dz2 = (uint16_t *)take((size_t)B * kH * 2);
+    mb->dg = (uint16_t *)take((size_t)B * kW * 2);
+    mb->dP = (uint16_t *)take((size_t)Nn * kW * 2);
+    mb->dP2 = (uint16_t *)take((size_t)Nn * kW * 2);
+    mb->dHM = (uint16_t *)take((size_t)Nn * 2 * kW * 2);
+    mb->part = (float *)take(part_floats * 4);
+    mb->part_floats = part_floats;
+  }
+  PS_TRY(c, hipMemcpyAsync(mb->node_atom, na.data(), (size_t)Nn * 4, hipMemcpyHostToDevice, c->stream));
+  PS_TRY(c, hipMemcpyAsync(mb->node_g0, ng0.data(), (size_t)Nn * 4, hipMemcpyHostToDevice, c->stream));
+  PS_TRY(c, hipMemcpyAsync(mb->node_graph, ngr.data(), (size_t)Nn * 4, hipMemcpyHostToDevice, c->stream));
+  PS_TRY(c, hipMemcpyAsync(mb->gstart, gstart.data(), (size_t)(B + 1) * 4, hipMemcpyHostToDevice, c->stream));
+  // the host vectors die here: wait for the copies
+  PS_TRY(c, hipStreamSynchronize(c->stream));
+  return AD_OK;
+}
+
+GemmArgs gemm_base(int M, int N, int K) {
+  GemmArgs g;
+  memset(&g, 0, sizeof(g));
+  g.M = M;
+  g.N = N;
+  g.K = K;
+  g.k_chunk = K;
+  return g;
+}
+
+hipError_t gemm(const GemmArgs &g, hipStream_t s, int zsplit = 1) {
+  dim3 grid(nblk(g.N, BN), nblk(g.M, BM), zsplit);
+  hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, s, g);
+  return hipGetLastError();
+}
+
+// weight gradient dW[Kin x Nout] = A^T . D with the reduction over R rows in
+// split-K chunks, summed in chunk order into `out`
+hipError_t wgrad(const GemmArgs &gbase, int R, float *part, size_t part_floats, float *out, hipStream_t s) {
+  GemmArgs g = gbase;
+  const int Z = std::max(1, (R + kSplitRows - 1) / kSplitRows);
+  g.k_chunk = kSplitRows;
+  g.part = part;
+  if ((size_t)Z * g.M * g.N > part_floats) return hipErrorInvalidValue;
+  hipError_t e = gemm(g, s, Z);
+  if (e != hipSuccess) return e;
+  const size_t MN = (size_t)g.M * g.N;
+  hipLaunchKernelGGL(k_reduce_parts, dim3(nblk(MN)), dim3(256), 0, s, part, Z, MN, out);
+  return hipGetLastError();
+}
+
+int forward(ad_prescreen *ps, const ad_batch *b, MB &mb) {
+  ad_ctx *c = ps->ctx;
+  hipStream_t s = c->stream;
+  const Offs &o = ps->o;
+  GraphArgs G{mb.node_atom, mb.node_g0, mb.node_graph, mb.gstart, b->ps_nbr, mb.Nn, mb.B};
+  hipLaunchKernelGGL(k_gather_x, dim3(nblk((size_t)mb.Nn * kFeat)), dim3(256), 0, s, G, b->ps_x, mb.Xmb);
+  GemmArgs g = gemm_base(mb.Nn, kW, kFeat);
+  g.a_mode = 0;
+  g.A1 = mb.Xmb;
+  g.lda1 = kFeat;
+  g.B = ps->wbf + o.W[0];
+  g.ldb = kW;
+  g.bias = ps->w + o.b[0];
+  g.relu = 1;
+  g.C16 = mb.H[0];
+  g.ldc16 = kW;
+  PS_TRY(c, gemm(g, s));
+  for (int l = 1; l <= kLayers; ++l) {
+    hipLaunchKernelGGL(k_neighbour_sum, dim3(nblk((size_t)mb.Nn * kW)), dim3(256), 0, s, G, mb.H[l - 1], mb.M[l]);
+    g = gemm_base(mb.Nn, kW, 2 * kW);
+    g.a_mode = 1;
+    g.split = kW;
+    g.A1 = mb.H[l - 1];
+    g.lda1 = kW;
+    g.A2 = mb.M[l];
+    g.lda2 = kW;
+    g.B = ps->wbf + o.W[l];
+    g.ldb = kW;
+    g.bias = ps->w + o.b[l];
+    g.relu = 1;
+    g.C16 = mb.H[l];
+    g.ldc16 = kW;
+    PS_TRY(c, gemm(g, s));
+  }
+  hipLaunchKernelGGL(k_pool, dim3(mb.B), dim3(kW), 0, s, G, mb.H[kLayers], mb.g);
+  g = gemm_base(mb.B, kH, kW);
+  g.A1 = mb.g;
+  g.lda1 = kW;
+  g.B = ps->wbf + o.U1;
+  g.ldb = kH;
+  g.bias = ps->w + o.c1;
+  g.relu = 1;
+  g.C16 = mb.z1;
+  g.ldc16 = kH;
+  PS_TRY(c, gemm(g, s));
+  g = gemm_base(mb.B, kH, kH);
+  g.A1 = mb.z1;
+  g.lda1 = kH;
+  g.B = ps->wbf + o.U2;
+  g.ldb = kH;
+  g.bias = ps->w + o.c2;
+  g.relu = 1;
+  g.C16 = mb.z2;
+  g.ldc16 = kH;
+  PS_TRY(c, gemm(g, s));
+  hipLaunchKernelGGL(k_head, dim3(mb.B), dim3(64), 0, s, mb.z2, ps->wbf + o.U3, ps->w + o.c3, mb.B, mb.p);
+  PS_TRY(c, hipGetLastError());
+  return AD_OK;
+}
+
+int backward(ad_prescreen *ps, const ad_batch *b, MB &mb) {
+  ad_ctx *c = ps->ctx;
+  hipStream_t s = c->stream;
+  const Offs &o = ps->o;
+  float *gr = ps->gr;
+  GraphArgs G{mb.node_atom, mb.node_g0, mb.node_graph, mb.gstart, b->ps_nbr, mb.Nn, mb.B};
+  hipLaunchKernelGGL(k_head_bwd, dim3(1), dim3(kH), 0, s, mb.z2, ps->wbf + o.U3, mb.dp, mb.B, mb.dz2, gr + o.U3,
+                     gr + o.c3);
+  // U2, c2; dz1
+  GemmArgs g = gemm_base(kH, kH, mb.B);
+  g.a_mode = 2;
+  g.A1 = mb.z1;
+  g.lda1 = kH;
+  g.B = mb.dz2;
+  g.ldb = kH;
+  PS_TRY(c, wgrad(g, mb.B, mb.part, mb.part_floats, gr + o.U2, s));
+  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(kH), 0, s, mb.dz2, mb.B, kH, gr + o.c2);
+  g = gemm_base(mb.B, kH, kH);
+  g.A1 = mb.dz2;
+  g.lda1 = kH;
+  g.b_mode = 1;
+  g.B = ps->wbf + o.U2;
+  g.ldb = kH;
+  g.mask = mb.z1;
+  g.ldm = kH;
+  g.C16 = mb.dz1;
+  g.ldc16 = kH;
+  PS_TRY(c, gemm(g, s));
+  // U1, c1; dg
+  g = gemm_base(kW, kH, mb.B);
+  g.a_mode = 2;
+  g.A1 = mb.g;
+  g.lda1 = kW;
+  g.B = mb.dz1;
+  g.ldb = kH;
+  PS_TRY(c, wgrad(g, mb.B, mb.part, mb.part_floats, gr + o.U1, s));
+  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(kH), 0, s, mb.dz1, mb.B, kH, gr + o.c1);
+  g = gemm_base(mb.B, kW, kH);
+  g.A1 = mb.dz1;
+  g.lda1 = kH;
+  g.b_mode = 1;
+  g.B = ps->wbf + o.U1;
+  g.ldb = kH;
+  g.C16 = mb.dg;
+  g.ldc16 = kW;
+  PS_TRY(c, gemm(g, s));
+  // pool backward, then the message-passing layers
+  uint16_t *dP = mb.dP, *dPn = mb.dP2;
+  hipLaunchKernelGGL(k_pool_bwd, dim3(nblk((size_t)mb.Nn * kW)), dim3(256), 0, s, G, mb.dg, mb.H[kLayers], dP);
+  for (int l = kLayers; l >= 1; --l) {
+    g = gemm_base(2 * kW, kW, mb.Nn);
+    g.a_mode = 3;
+    g.split = kW;
+    g.A1 = mb.H[l - 1];
+    g.lda1 = kW;
+    g.A2 = mb.M[l];
+    g.lda2 = kW;
+    g.B = dP;
+    g.ldb = kW;
+    PS_TRY(c, wgrad(g, mb.Nn, mb.part, mb.part_floats, gr + o.W[l], s));
+    hipLaunchKernelGGL(k_colsum, dim3(1), dim3(kW), 0, s, dP, mb.Nn, kW, gr + o.b[l]);
+    g = gemm_base(mb.Nn, 2 * kW, kW);
+    g.A1 = dP;
+    g.lda1 = kW;
+    g.b_mode = 1;
+    g.B = ps->wbf + o.W[l];
+    g.ldb = kW;
+    g.C16 = mb.dHM;
+    g.ldc16 = 2 * kW;
+    PS_TRY(c, gemm(g, s));
+    hipLaunchKernelGGL(k_neighbour_bwd, dim3(nblk((size_t)mb.Nn * kW)), dim3(256), 0, s, G, mb.dHM, mb.H[l - 1],
+                       dPn);
+    std::swap(dP, dPn);
+  }
+  g = gemm_base(kFeat, kW, mb.Nn);
+  g.a_mode = 2;
+  g.A1 = mb.Xmb;
+  g.lda1 = kFeat;
+  g.B = dP;
+  g.ldb = kW;
+  PS_TRY(c, wgrad(g, mb.Nn, mb.part, mb.part_floats, gr + o.W[0], s));
+  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(kW), 0, s, dP, mb.Nn, kW, gr + o.b[0]);
+  PS_TRY(c, hipGetLastError());
+  return AD_OK;
+}
+
+int check_ps(ad_prescreen *ps, const ad_batch *b, int n, const int *idx) {
+  if (!ps) return AD_E_INVALID;
+  ad_ctx *c = ps->ctx;
+  if (!b || b->ctx != c) return c->fail(AD_E_INVALID, "bad batch");
+  if (!b->ps_ok) return c->fail(AD_E_INVALID, "batch has atoms with more than 8 bonds (pre-screen limit)");
+  if (n < 0) return c->fail(AD_E_INVALID, "n < 0");
+  if (idx)
+    for (int i = 0; i < n; ++i)
+      if (idx[i] < 0 || idx[i] >= b->n_lig) return c->fail(AD_E_INVALID, "ligand index out of range");
+  return AD_OK;
+}
+
+}  // namespace
+
+extern "C" int ad_prescreen_create(ad_ctx *c, const ad_prescreen_cfg *cfg, uint64_t seed, ad_prescreen **out) {
+  if (!c || !out) return AD_E_INVALID;
+  *out = nullptr;
+  ad_prescreen_cfg d;
+  d.batch_size = 256;
+  d.lr = 1e-3;
+  d.lam = 1.0;
+  d.tau = 0.5;
+  d.beta1 = 0.9;
+  d.beta2 = 0.999;
+  d.eps = 1e-8;
+  d.label_max = HUGE_VAL;
+  if (cfg) d = *cfg;
+  if (d.batch_size < 2 || d.batch_size > 4096 || !(d.lr > 0) || !(d.tau > 0) || !(d.lam >= 0) ||
+      !(d.beta1 >= 0 && d.beta1 < 1) || !(d.beta2 >= 0 && d.beta2 < 1) || !(d.eps > 0) || std::isnan(d.label_max))
+    return c->fail(AD_E_INVALID, "bad pre-screen configuration");
+  hipSetDevice(c->device);
+  ad_prescreen *ps = new ad_prescreen();
+  ps->ctx = c;
+  ps->cfg = d;
+  ps->o = make_offs();
+  const size_t P = ps->o.total;
+  if (hipMalloc(&ps->w, P * 4) != hipSuccess || hipMalloc(&ps->gr, P * 4) != hipSuccess ||
+      hipMalloc(&ps->m, P * 4) != hipSuccess || hipMalloc(&ps->v, P * 4) != hipSuccess ||
+      hipMalloc(&ps->wbf, P * 2) != hipSuccess) {
+    ad_prescreen_destroy(ps);
+    return c->fail(AD_E_OOM, "cannot allocate pre-screen parameters");
+  }
+  // He-uniform weights, zero biases (host RNG seeded by `seed`)
+  std::vector<float> w(P, 0.0f);
+  std::mt19937_64 rng(seed);
+  auto fill = [&](size_t off, int fan_in, size_t n) {
+    std::uniform_real_distribution<double> u(-std::sqrt(6.0 / fan_in), std::sqrt(6.0 / fan_in));
+    for (size_t i = 0; i < n; ++i) w[off + i] = (float)u(rng);
+  };
+  const Offs &o = ps->o;
+  fill(o.W[0], kFeat, (size_t)kFeat * kW);
+  for (int l = 1; l <= kLayers; ++l) fill(o.W[l], 2 * kW, (size_t)2 * kW * kW);
+  fill(o.U1, kW, (size_t)kW * kH);
+  fill(o.U2, kH, (size_t)kH * kH);
+  fill(o.U3, kH, kH);
+  // a small output layer starts the predictions near the label mean
+  for (int i = 0; i < kH; ++i) w[o.U3 + i] *= 0.01f;
+  int rc = ad_prescreen_set_params(ps, w.data());
+  if (rc) {
+    ad_prescreen_destroy(ps);
+    return rc;
+  }
+  *out = ps;
+  return AD_OK;
+}
+
+extern "C" void ad_prescreen_destroy(ad_prescreen *ps) {
+  if (!ps) return;
+  hipSetDevice(ps->ctx->device);
+  hipStreamSynchronize(ps->ctx->stream);
+  hipFree(ps->w);
+  hipFree(ps->gr);
+  hipFree(ps->m);
+  hipFree(ps->v);
+  hipFree(ps->wbf);
+  hipFree(ps->work);
+  delete ps;
+}
+
+extern "C" int ad_prescreen_n_params(void) { return (int)make_offs().total; }
+
+extern "C" int ad_prescreen_set_params(ad_prescreen *ps, const float *params) {
+  if (!ps || !params) return AD_E_INVALID;
+  ad_ctx *c = ps->ctx;
+  const size_t P = ps->o.total;
+  for (size_t i = 0; i < P; ++i)
+    if (!std::isfinite(params[i])) return c->fail(AD_E_INVALID, "non-finite parameter");
+  hipSetDevice(c->device);
+  PS_TRY(c, hipMemcpyAsync(ps->w, params, P * 4, hipMemcpyHostToDevice, c->stream));
+  PS_TRY(c, hipMemsetAsync(ps->m, 0, P * 4, c->stream));
+  PS_TRY(c, hipMemsetAsync(ps->v, 0, P * 4, c->stream));
+  hipLaunchKernelGGL(k_cast, dim3(nblk(P)), dim3(256), 0, c->stream, ps->w, P, ps->wbf);
+  PS_TRY(c, hipGetLastError());
+  PS_TRY(c, hipStreamSynchronize(c->stream));
+  ps->step = 0;
+  return AD_OK;
+}
+
+extern "C" int ad_prescreen_get_params(ad_prescreen *ps, float *params) {
+  if (!ps || !params) return AD_E_INVALID;
+  ad_ctx *c = ps->ctx;
+  hipSetDevice(c->device);
+  PS_TRY(c, hipMemcpyAsync(params, ps->w, ps->o.total * 4, hipMemcpyDeviceToHost, c->stream));
+  PS_TRY(c, hipStreamSynchronize(c->stream));
+  return AD_OK;
+}
+
+extern "C" int ad_prescreen_set_scale(ad_prescreen *ps, double mean, double sd) {
+  if (!ps || !std::isfinite(mean) || !(sd > 0) || !std::isfinite(sd)) return AD_E_INVALID;
+  ps->mean = mean;
+  ps->sd = sd;
+  return AD_OK;
+}
+
+extern "C" int ad_prescreen_predict(ad_prescreen *ps, const ad_batch *b, int n, const int *lig_idx, float *scores) {
+  int rc = check_ps(ps, b, n, lig_idx);
+  if (rc) return rc;
+  if (n == 0) return AD_OK;
+  if (!scores) return ps->ctx->fail(AD_E_INVALID, "null scores");
+  ad_ctx *c = ps->ctx;
+  hipSetDevice(c->device);
+  const int chunk = 2048;
+  std::vector<int> sel(chunk);
+  for (int s0 = 0; s0 < n; s0 += chunk) {
+    const int B = std::min(chunk, n - s0);
+    for (int i = 0; i < B; ++i) sel[i] = lig_idx ? lig_idx[s0 + i] : s0 + i;
+    MB mb;
+    rc = setup_mb(ps, b, sel.data(), B, false, &mb);
+    if (rc) return rc;
+    rc = forward(ps, b, mb);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_unscale, dim3(nblk(B)), dim3(256), 0, c->stream, mb.p, B, (float)ps->mean, (float)ps->sd,
+                       mb.y);
+    PS_TRY(c, hipMemcpyAsync(scores + s0, mb.y, (size_t)B * 4, hipMemcpyDeviceToHost, c->stream));
+    PS_TRY(c, hipStreamSynchronize(c->stream));
+  }
+  return AD_OK;
+}
+
+namespace {
+
+// forward + loss + backward on one minibatch given on the host
+int step_grad(ad_prescreen *ps, const ad_batch *b, const int *sel, int B, const float *labels_std_host, MB *mbo) {
+  ad_ctx *c = ps->ctx;
+  MB mb;
+  int rc = setup_mb(ps, b, sel, B, true, &mb);
+  if (rc) return rc;
+  PS_TRY(c, hipMemcpyAsync(mb.y, labels_std_host, (size_t)B * 4, hipMemcpyHostToDevice, c->stream));
+  rc = forward(ps, b, mb);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_loss, dim3(1), dim3(256), 0, c->stream, mb.p, mb.y, B, (float)ps->cfg.lam,
+                     (float)ps->cfg.tau, mb.loss, mb.dp);
+  rc = backward(ps, b, mb);
+  if (rc) return rc;
+  *mbo = mb;
+  return AD_OK;
+}
+
+}  // namespace
+
+extern "C" int ad_prescreen_grad(ad_prescreen *ps, const ad_batch *b, int n, const int *lig_idx, const float *labels,
+                                 float *loss, float *grad, float *pred_std) {
+  int rc = check_ps(ps, b, n, lig_idx);
+  if (rc) return rc;
+  ad_ctx *c = ps->ctx;
+  if (n < 2 || n > 4096 || !labels) return c->fail(AD_E_INVALID, "need 2..4096 labelled ligands");
+  hipSetDevice(c->device);
+  std::vector<int> sel(n);
+  std::vector<float> ys(n);
+  for (int i = 0; i < n; ++i) {
+    sel[i] = lig_idx ? lig_idx[i] : i;
+    ys[i] = (float)((std::min((double)labels[i], ps->cfg.label_max) - ps->mean) / ps->sd);
+  }
+  MB mb;
+  rc = step_grad(ps, b, sel.data(), n, ys.data(), &mb);
+  if (rc) return rc;
+  if (loss) PS_TRY(c, hipMemcpyAsync(loss, mb.loss, 4, hipMemcpyDeviceToHost, c->stream));
+  if (grad) PS_TRY(c, hipMemcpyAsync(grad, ps->gr, ps->o.total * 4, hipMemcpyDeviceToHost, c->stream));
+  if (pred_std) PS_TRY(c, hipMemcpyAsync(pred_std, mb.p, (size_t)n * 4, hipMemcpyDeviceToHost, c->stream));
+  PS_TRY(c, hipStreamSynchronize(c->stream));
+  return AD_OK;
+}
+
+extern "C" int ad_prescreen_train(ad_prescreen *ps, const ad_batch *b, int n, const int *lig_idx,
+                                  const float *labels, int epochs, uint64_t seed, float *loss_curve) {
+  int rc = check_ps(ps, b, n, lig_idx);
+  if (rc) return rc;
+  ad_ctx *c = ps->ctx;
+  if (n < 2 || epochs < 0 || !labels) return c->fail(AD_E_INVALID, "need >= 2 labelled ligands, epochs >= 0");
+  for (int i = 0; i < n; ++i)
+    if (!std::isfinite(labels[i])) return c->fail(AD_E_INVALID, "non-finite label");
+  hipSetDevice(c->device);
+  // clip, then standardise the labels
+  std::vector<double> yc(n);
+  for (int i = 0; i < n; ++i) yc[i] = std::min((double)labels[i], ps->cfg.label_max);
+  double mu = 0, var = 0;
+  for (int i = 0; i < n; ++i) mu += yc[i];
+  mu /= n;
+  for (int i = 0; i < n; ++i) var += (yc[i] - mu) * (yc[i] - mu);
+  const double sd = std::sqrt(var / n) > 1e-12 ? std::sqrt(var / n) : 1.0;
+  ps->mean = mu;
+  ps->sd = sd;
+  std::vector<int> order(n);
+  std::iota(order.begin(), order.end(), 0);
+  const int Bsz = std::min(ps->cfg.batch_size, n);
+  std::vector<int> sel(Bsz);
+  std::vector<float> ys(Bsz);
+  std::mt19937_64 rng(seed);
+  const size_t P = ps->o.total;
+  for (int ep = 0; ep < epochs; ++ep) {
+    std::shuffle(order.begin(), order.end(), rng);
+    double lsum = 0;
+    int nb = 0;
+    for (int s0 = 0; s0 + Bsz <= n; s0 += Bsz) {
+      for (int i = 0; i < Bsz; ++i) {
+        const int k = order[s0 + i];
+        sel[i] = lig_idx ? lig_idx[k] : k;
+        ys[i] = (float)((yc[k] - mu) / sd);
+      }
+      MB mb;
+      rc = step_grad(ps, b, sel.data(), Bsz, ys.data(), &mb);
+      if (rc) return rc;
+      ps->step += 1;
+      const float c1 = 1.0f - (float)std::pow(ps->cfg.beta1, (double)ps->step);
+      const float c2 = 1.0f - (float)std::pow(ps->cfg.beta2, (double)ps->step);
+      hipLaunchKernelGGL(k_adam, dim3(nblk(P)), dim3(256), 0, c->stream, ps->w, ps->gr, ps->m, ps->v, P,
+                         (float)ps->cfg.lr, (float)ps->cfg.beta1, (float)ps->cfg.beta2, (float)ps->cfg.eps, c1, c2,
+                         ps->wbf);
+      PS_TRY(c, hipGetLastError());
+      float l = 0;
+      PS_TRY(c, hipMemcpyAsync(&l, mb.loss, 4, hipMemcpyDeviceToHost, c->stream));
+      PS_TRY(c, hipStreamSynchronize(c->stream));
+      lsum += l;
+      ++nb;
+    }
+    if (loss_curve) loss_curve[ep] = nb ? (float)(lsum / nb) : 0.0f;
+  }
+  return AD_OK;
+}
+
+extern "C" int ad_prescreen_get_scale(ad_prescreen *ps, double *mean, double *sd) {
+  if (!ps) return AD_E_INVALID;
+  if (mean) *mean = ps->mean;
+  if (sd) *sd = ps->sd;
+  return AD_OK;
+}

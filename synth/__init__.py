@@ -10,7 +10,10 @@ Every generator takes an integer seed and is deterministic (numpy PCG64).
 """
 from __future__ import annotations
 
+import ctypes
 import math
+import os
+import subprocess
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -343,6 +346,74 @@ def ligand_set(seed: int, n_ligands: int, atoms=(15, 60), torsions=(0, 15),
             n = lognormal_atoms(rng, lo=atoms[0], hi=atoms[1])
         t = int(rng.integers(torsions[0], torsions[1] + 1))
         out.append(ligand(int(rng.integers(1 << 62)), n, t, freqs=freqs))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Fast C generator for large ligand sets (same recipe, its own random stream)
+# ---------------------------------------------------------------------------
+_LIGEN_SRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "ligen.c")
+_LIGEN_LIB = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libligen.so")
+_ligen = None
+
+
+def build_ligen() -> str:
+    """Compile synth/ligen.c (gcc -O2 -fopenmp) into synth/libligen.so."""
+    tmp = _LIGEN_LIB + ".tmp"
+    subprocess.run(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", _LIGEN_SRC, "-o", tmp, "-lm"], check=True,
+                   capture_output=True)
+    os.replace(tmp, _LIGEN_LIB)
+    return _LIGEN_LIB
+
+
+def _ligen_lib():
+    global _ligen
+    if _ligen is None:
+        if not os.path.exists(_LIGEN_LIB) or os.path.getmtime(_LIGEN_LIB) < os.path.getmtime(_LIGEN_SRC):
+            build_ligen()
+        L = ctypes.CDLL(_LIGEN_LIB)
+        vp = ctypes.c_void_p
+        L.lg_ligand_set.argtypes = [ctypes.c_uint64, ctypes.c_int, vp, vp, vp, ctypes.c_double, vp, vp, vp, vp, vp]
+        L.lg_ligand_set.restype = ctypes.c_int
+        _ligen = L
+    return _ligen
+
+
+def ligand_set_fast(seed: int, n_ligands: int, atoms=(10, 100), torsions=(0, 32), dist="lognormal",
+                    freqs=FREQ_SIX, min_nonlocal: float = 2.0) -> list:
+    """Like ligand_set, generated by the C generator (about 10^5 ligands/s on
+    8 cores).  Sizes and torsion requests are drawn here with numpy from
+    `seed`; ligand i is grown from seed * 2^20 + i."""
+    rng = np.random.default_rng(np.random.PCG64(seed))
+    if dist == "uniform":
+        n = rng.integers(atoms[0], atoms[1] + 1, size=n_ligands)
+    else:
+        n = np.array([lognormal_atoms(rng, lo=atoms[0], hi=atoms[1]) for _ in range(n_ligands)])
+    t = rng.integers(torsions[0], torsions[1] + 1, size=n_ligands)
+    n = np.ascontiguousarray(n, dtype=np.int32)
+    t = np.ascontiguousarray(t, dtype=np.int32)
+    fr = np.zeros(len(TYPE_TABLE), dtype=np.float64)
+    for k, v in freqs.items():
+        fr[TYPE_ID[k]] = v
+    na = int(n.sum())
+    nb = int(np.maximum(n - 1, 0).sum())
+    types = np.empty(na, np.int32)
+    q = np.empty(na, np.float32)
+    xyz = np.empty((na, 3), np.float32)
+    bonds = np.empty((max(nb, 1), 2), np.int32)
+    rot = np.empty(max(nb, 1), np.uint8)
+    rc = _ligen_lib().lg_ligand_set((seed << 20) & (2**64 - 1), n_ligands, n.ctypes.data, t.ctypes.data,
+                                    fr.ctypes.data, min_nonlocal, types.ctypes.data, q.ctypes.data,
+                                    xyz.ctypes.data, bonds.ctypes.data, rot.ctypes.data)
+    if rc:
+        raise RuntimeError(f"C ligand generator failed on ligand {-rc - 1}")
+    out = []
+    a = b = 0
+    for i in range(n_ligands):
+        k = int(n[i])
+        out.append(Ligand(types[a:a + k], q[a:a + k], xyz[a:a + k], bonds[b:b + k - 1], rot[b:b + k - 1]))
+        a += k
+        b += k - 1
     return out
 
 

@@ -1,0 +1,90 @@
+"""Checks of the seeded input generators (CPU): the ligands they emit are
+valid typed trees with the stated geometry, for the Python and the C
+generator alike."""
+import numpy as np
+import pytest
+
+import synth
+
+
+def check_ligand(lig, min_nonlocal=2.0):
+    n = lig.n_atoms
+    b = np.asarray(lig.bonds).reshape(-1, 2)
+    assert len(b) == n - 1 and len(lig.rotatable) == n - 1
+    # a tree: n-1 bonds connecting every atom
+    parent = list(range(n))
+
+    def find(u):
+        while parent[u] != u:
+            parent[u] = parent[parent[u]]
+            u = parent[u]
+        return u
+
+    for u, v in b:
+        ru, rv = find(int(u)), find(int(v))
+        assert ru != rv
+        parent[ru] = rv
+    deg = np.bincount(b.ravel(), minlength=n) if n > 1 else np.zeros(1, int)
+    for i in range(n):
+        assert deg[i] <= synth.MAX_VALENCE[synth.TYPE_NAMES[lig.types[i]]]
+        if synth.TYPE_NAMES[lig.types[i]] == "HD":
+            assert deg[i] == 1
+            j = int(b[np.where((b == i).any(axis=1))[0][0]].sum() - i)
+            assert synth.TYPE_NAMES[lig.types[j]] in ("N", "OA")
+    if n > 1:
+        d = np.linalg.norm(lig.xyz[b[:, 0]] - lig.xyz[b[:, 1]], axis=1)
+        assert d.min() >= 1.0 - 1e-5 and d.max() <= 1.55 + 1e-5
+    # rotatable bonds join two atoms of degree >= 2
+    for k in np.where(lig.rotatable)[0]:
+        assert deg[b[k, 0]] >= 2 and deg[b[k, 1]] >= 2
+    # bond-path distances and clash rules
+    adj = [[] for _ in range(n)]
+    for u, v in b:
+        adj[u].append(v)
+        adj[v].append(u)
+    for s in range(n):
+        dist = {s: 0}
+        stack = [s]
+        while stack:
+            u = stack.pop()
+            for v in adj[u]:
+                if v not in dist:
+                    dist[v] = dist[u] + 1
+                    stack.append(v)
+        r = np.linalg.norm(lig.xyz - lig.xyz[s], axis=1)
+        for j in range(n):
+            if dist[j] == 2:
+                assert r[j] >= 1.2 - 1e-4
+            elif dist[j] >= 3:
+                assert r[j] >= min_nonlocal - 1e-4
+    assert abs(float(np.sum(lig.charges, dtype=np.float64))) < 1e-4
+    assert np.allclose(lig.xyz.mean(axis=0), 0.0, atol=1e-4)
+
+
+@pytest.mark.parametrize("n,t", [(1, 0), (2, 0), (3, 1), (24, 5), (60, 15), (100, 32)])
+def test_python_ligand_is_valid(n, t):
+    lig = synth.ligand(n * 7 + t, n, t)
+    check_ligand(lig)
+    assert lig.n_torsions <= t
+
+
+def test_fast_ligand_set_is_valid_and_seeded():
+    L = synth.ligand_set_fast(3, 300)
+    for lig in L[:120]:
+        check_ligand(lig)
+    n = np.array([l.n_atoms for l in L])
+    assert n.min() >= 10 and n.max() <= 100 and 25 <= np.median(n) <= 40
+    again = synth.ligand_set_fast(3, 5)
+    for a, b in zip(L, again):
+        assert np.array_equal(a.xyz, b.xyz) and np.array_equal(a.types, b.types)
+    other = synth.ligand_set_fast(4, 5)
+    assert not all(np.array_equal(a.types, b.types) for a, b in zip(L, other))
+
+
+def test_fast_ligand_type_frequencies():
+    L = synth.ligand_set_fast(9, 2000, atoms=(20, 40), dist="uniform")
+    t = np.concatenate([l.types for l in L])
+    f = np.bincount(t, minlength=len(synth.TYPE_TABLE)) / len(t)
+    for name, p in synth.FREQ_SIX.items():
+        # HD that finds no host becomes C, so allow a small shift between the two
+        assert abs(f[synth.TYPE_ID[name]] - p) < (0.02 if name in ("C", "HD") else 0.01), name
