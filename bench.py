@@ -81,6 +81,115 @@ def cpu_baseline(c, dock, seconds, log_fn):
                         f"evaluation count to {evals_per_ligand} evaluations per ligand"))
 
 
+def screened_campaign(args, log_fn):
+    """Plain against screened docking (the screening setting: many ligands,
+    one receptor).  The pre-screen is trained on the GPU on labels that plain
+    docking produces (5 runs x population 100 on the 8,000-atom receptor's
+    64^3 grid), then ranks the campaign set (126^3 grid over the same
+    receptor); the top fraction is docked with the campaign's parameters.  A
+    random holdout docked in full is the judge of recall and gives the plain
+    rate."""
+    import numpy as np
+    import torch
+
+    import paper_2007_03678_amd as pkg
+    import synth
+    from paper_2007_03678_amd import screen
+
+    seed = 20200707
+    ff = synth.forcefield()
+    ctx = pkg.create(ff, 0)
+    rec = synth.receptor(seed, 8000)
+    out = {}
+    # -- labels and training ------------------------------------------------
+    t0 = time.time()
+    ctx.ad_build_grids(synth.make_grid(64, 0.375, map_types=synth.ALL_TYPES), rec)
+    train = synth.ligand_set_fast(seed + 11, args.train_ligands, atoms=(10, 100), torsions=(0, 32),
+                                  dist="lognormal")
+    tb = ctx.ad_load_ligands(train)
+    log_fn(f"campaign: {len(train)} training ligands generated and loaded in {time.time() - t0:.1f}s")
+    p_lab = pkg.make_params(nrun=5, pop=100, max_gens=args.label_gens, ls_rate=0.06, ls_iters=300)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lab = ctx.ad_dock_batch(tb, p_lab, seed)
+    t_label = time.perf_counter() - t0
+    y = lab["best_energy"].astype(np.float64)
+    log_fn(f"campaign: labels by plain docking in {t_label:.1f}s")
+    ps = pkg.Prescreen(ctx, seed=1, label_max=0.0)
+    t0 = time.perf_counter()
+    curve = ps.ad_prescreen_train(tb, None, y, epochs=args.epochs, seed=2)
+    t_train = time.perf_counter() - t0
+    log_fn(f"campaign: pre-screen trained in {t_train:.1f}s, loss {curve[0]:.3f} -> {curve[-1]:.3f}")
+    tb.free()
+    # -- campaign set --------------------------------------------------------
+    t0 = time.time()
+    grid = synth.make_grid(126, 0.375, map_types=synth.ALL_TYPES)
+    ctx.ad_build_grids(grid, rec)
+    camp = synth.ligand_set_fast(seed + 12, args.campaign_ligands, atoms=(10, 100), torsions=(0, 32),
+                                 dist="lognormal")
+    cb = ctx.ad_load_ligands(camp)
+    torch.cuda.synchronize()
+    log_fn(f"campaign: {len(camp)} ligands generated and loaded, 126^3 maps built in {time.time() - t0:.1f}s")
+    n = len(camp)
+    p_full = pkg.make_params(nrun=20, pop=150, max_gens=10**9, max_evals=args.campaign_evals, ls_rate=0.06,
+                             ls_iters=300)
+    # screened step: rank every ligand, dock the top fraction
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pred = ps.ad_prescreen_predict(cb)
+    t_pred = time.perf_counter() - t0
+    sel = screen.top_fraction(pred, args.screen_frac).astype(np.int32)
+    r_sel = ctx.ad_dock_select(cb, sel, p_full, seed)
+    t_screened = time.perf_counter() - t0
+    log_fn(f"campaign: screened step (rank {n}, dock {len(sel)}) {t_screened:.1f}s")
+    # judge: a random holdout docked in full (the plain rate and recall)
+    hold = np.sort(np.random.default_rng(seed).choice(n, size=min(args.holdout, n), replace=False)).astype(np.int32)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r_hold = ctx.ad_dock_select(cb, hold, p_full, seed)
+    t_hold = time.perf_counter() - t0
+    log_fn(f"campaign: holdout of {len(hold)} docked in {t_hold:.1f}s")
+    judge = r_hold["best_energy"].astype(np.float64)
+    ph = pred[hold]
+    hits, pos = screen.recall(judge, screen.top_fraction(ph, args.screen_frac), top_frac=0.01)
+    lo, hi = screen.clopper_pearson(hits, pos)
+    f95 = screen.fraction_for_recall(ph, judge, 0.95, 0.01)
+    plain_rate = len(hold) / t_hold
+    from scipy.stats import spearmanr
+    rho = float(spearmanr(ph, judge)[0])
+    nat = np.array([camp[i].n_atoms for i in hold], dtype=np.float64)
+    size_hits, _ = screen.recall(judge, screen.top_fraction(-nat, args.screen_frac), top_frac=0.01)
+    evals_sel = int(r_sel["evals"].sum())
+    out = {
+        "workload": (f"campaign: {n} ligands (atoms lognormal median 32 in 10-100, torsions 0-32), 8,000-atom "
+                     f"receptor, 126^3 x 10 FP32 maps, 20 runs x pop 150, cap {args.campaign_evals} evals/run; "
+                     f"pre-screen trained on {len(train)} ligands labelled by plain docking (5 runs x pop 100, "
+                     f"{args.label_gens} generations, 64^3 grid)"),
+        "plain_ligands_per_s": round(plain_rate, 3),
+        "screened_ligands_per_s": round(n / t_screened, 3),
+        "speedup": round(n / t_screened / plain_rate, 2),
+        "frac_docked": args.screen_frac,
+        "n_docked": int(len(sel)),
+        "screened_step_s": round(t_screened, 2),
+        "predict_ligands_per_s": round(n / t_pred, 1),
+        "recall_top1pct": round(hits / pos, 4),
+        "recall_hits": [int(hits), int(pos)],
+        "recall_ci95": [round(lo, 4), round(hi, 4)],
+        "size_heuristic_recall": round(size_hits / pos, 4),
+        "holdout_spearman": round(rho, 4),
+        "frac_for_95pct_recall": round(f95, 4),
+        "screened_ligands_per_s_at_95pct_recall_derived": round(n / (t_pred + f95 * n / plain_rate), 3),
+        "screened_evals_per_s": round(evals_sel / (t_screened - t_pred), 1),
+        "train": {"ligands": len(train), "epochs": args.epochs, "label_dock_s": round(t_label, 2),
+                  "train_s": round(t_train, 2), "graphs_per_s": round(len(train) * args.epochs / t_train, 1),
+                  "loss_first_epoch": round(float(curve[0]), 4), "loss_last_epoch": round(float(curve[-1]), 4)},
+    }
+    ps.close()
+    cb.free()
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -89,6 +198,14 @@ def main():
     ap.add_argument("--workload", default="screen64")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-campaign", action="store_true", help="skip the plain-vs-screened campaign")
+    ap.add_argument("--campaign-ligands", type=int, default=65536)
+    ap.add_argument("--train-ligands", type=int, default=32768)
+    ap.add_argument("--label-gens", type=int, default=10)
+    ap.add_argument("--epochs", type=int, default=15)
+    ap.add_argument("--campaign-evals", type=int, default=100_000, help="evaluation cap per run in the campaign")
+    ap.add_argument("--holdout", type=int, default=2048)
+    ap.add_argument("--screen-frac", type=float, default=0.1)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -188,11 +305,13 @@ def main():
     }
     # score-grad evaluations per second inside the local-search kernel
     out["score_grad_evals_per_s"] = round(dock["nrun"] * n_lig * n_ls * dock["ls_iters"] / ls_avg_s, 1)
+    batch.free()
+    ctx.close()
+    if not args.no_campaign:
+        out["screened"] = screened_campaign(args, log)
     if not args.no_cpu_baseline:
         log("cpu baseline: running the oracle")
         out["cpu_baseline"] = cpu_baseline(c, dock, args.cpu_seconds, log)
-    batch.free()
-    ctx.close()
     print(json.dumps(out), flush=True)
 
 

@@ -217,6 +217,16 @@ typedef struct {
 int ad_dock_batch(ad_ctx *ctx, const ad_batch *b, const ad_dock_params *p, uint64_t seed, const uint32_t *lig_ids,
                   ad_dock_result *out, float *run_energy, float *run_genotype);
 
+/* ad_dock_select: docks the n ligands lig_idx[0..n) (batch indices, host)
+ * of batch b exactly as ad_dock_batch docks them (a ligand's random streams
+ * are keyed by its batch index, so its result does not depend on which
+ * other ligands are docked with it).  out: [n] results, run_energy [n][nrun]
+ * and run_genotype [n][nrun][40] (optional), host.  Serves a screened
+ * campaign: dock only the ligands a pre-screen ranks best (Sec. 2.2: many
+ * ligands against one receptor).  Errors as ad_dock_batch. */
+int ad_dock_select(ad_ctx *ctx, const ad_batch *b, int n, const int *lig_idx, const ad_dock_params *p, uint64_t seed,
+                   ad_dock_result *out, float *run_energy, float *run_genotype);
+
 /* ad_local_search: ADADELTA on n given poses (genotypes in/out, [n][40]):
  * `iters` evaluations each; on return genotypes hold the best evaluated
  * pose and energy its energy (Lamarckian write-back).  Uses p->rho, p->eps. */
@@ -227,6 +237,23 @@ int ad_local_search(ad_ctx *ctx, const ad_batch *b, int n, const int *lig_idx, f
  * (ligand, run), [pop][40] host, exactly as ad_dock_batch draws them. */
 int ad_initial_population(ad_ctx *ctx, const ad_batch *b, int lig, uint32_t lig_id, int run, int pop,
                           uint64_t seed, float *genotypes);
+
+/* ---- docking schedule -------------------------------------------------------
+ * Batched uneven docking (Sec. 2.2: many ligands of different sizes against
+ * one receptor): the runs of a dock call are split into two atom-capacity
+ * buckets (<= 64 and <= 128 atoms), each served by its own kernel variant,
+ * in longest-first order, on two streams.  The generation loop is captured
+ * once per call into a hipGraph and replayed (use_graph; kernel timing
+ * forces eager launches).  The local-search kernel can stage the first
+ * stage_pairs pair records of each ligand in LDS; with autotune the size is
+ * chosen per bucket by timing short local searches on a copy of the initial
+ * population (cached per batch and shape), with stage_pairs >= 0 it is
+ * forced (rounded down to a candidate: 0, 128, 256, 512, 1024, 2048).  Every
+ * schedule computes identical results.  Defaults: graph on, autotune on. */
+int ad_set_schedule(ad_ctx *ctx, int use_graph, int autotune, int stage_pairs);
+/* stage_pairs[2]: the staging size used per bucket by the last dock call
+ * (-1: bucket empty or no local search); graph_used: 1 if it ran as a graph. */
+int ad_get_schedule(ad_ctx *ctx, int *stage_pairs, int *graph_used);
 
 /* ---- diagnostics ----------------------------------------------------------
  * Kernel timing with HIP events recorded on the context's stream around

@@ -26,8 +26,9 @@ MAX_TYPES, STRIDE = 16, 40
 
 EXPORTS = ["ad_create", "ad_destroy", "ad_last_error", "ad_set_stream", "ad_synchronize", "ad_load_grids",
            "ad_build_grids", "ad_ligand_check", "ad_load_ligands", "ad_free_batch", "ad_batch_info",
-           "ad_score_poses", "ad_dock_batch", "ad_local_search", "ad_initial_population",
-           "ad_set_kernel_timing", "ad_get_kernel_timing", "ad_prescreen_n_params", "ad_prescreen_create",
+           "ad_score_poses", "ad_dock_batch", "ad_dock_select", "ad_local_search", "ad_initial_population",
+           "ad_set_kernel_timing", "ad_get_kernel_timing", "ad_set_schedule", "ad_get_schedule",
+           "ad_prescreen_n_params", "ad_prescreen_create",
            "ad_prescreen_destroy", "ad_prescreen_set_params", "ad_prescreen_get_params", "ad_prescreen_set_scale",
            "ad_prescreen_get_scale", "ad_prescreen_predict", "ad_prescreen_grad", "ad_prescreen_train"]
 
@@ -142,8 +143,12 @@ def lib():
     L.ad_get_kernel_timing.argtypes = [vp, C.POINTER(KernelTimes), C.c_int]
     L.ad_score_poses.argtypes = [vp, vp, C.c_int, vp, vp, vp, vp, vp, C.c_int]
     L.ad_dock_batch.argtypes = [vp, vp, C.POINTER(DockParams), C.c_uint64, vp, C.POINTER(DockResult), fp, fp]
+    L.ad_dock_select.argtypes = [vp, vp, C.c_int, vp, C.POINTER(DockParams), C.c_uint64, C.POINTER(DockResult), fp,
+                                 fp]
     L.ad_local_search.argtypes = [vp, vp, C.c_int, vp, vp, vp, C.POINTER(DockParams), C.c_int, C.c_int]
     L.ad_initial_population.argtypes = [vp, vp, C.c_int, C.c_uint32, C.c_int, C.c_int, C.c_uint64, fp]
+    L.ad_set_schedule.argtypes = [vp, C.c_int, C.c_int, C.c_int]
+    L.ad_get_schedule.argtypes = [vp, ip, ip]
     L.ad_prescreen_n_params.argtypes = []
     L.ad_prescreen_create.argtypes = [vp, C.POINTER(PrescreenCfg), C.c_uint64, C.POINTER(vp)]
     L.ad_prescreen_destroy.argtypes = [vp]
@@ -297,6 +302,15 @@ class Context:
         self._check(lib().ad_get_kernel_timing(self.h, C.byref(t), 1 if reset else 0))
         return {k: (t.ms[i], int(t.launches[i])) for i, k in enumerate(KERNEL_KINDS)}
 
+    def ad_set_schedule(self, use_graph=True, autotune=True, stage_pairs=-1):
+        self._check(lib().ad_set_schedule(self.h, int(use_graph), int(autotune), int(stage_pairs)))
+
+    def ad_get_schedule(self):
+        st = (C.c_int * 2)()
+        g = C.c_int()
+        self._check(lib().ad_get_schedule(self.h, st, C.byref(g)))
+        return dict(stage_pairs=[st[0], st[1]], graph=bool(g.value))
+
     def ad_synchronize(self):
         self._check(lib().ad_synchronize(self.h))
 
@@ -381,6 +395,21 @@ class Context:
         self._check(lib().ad_dock_batch(self.h, batch.h, C.byref(params), seed, _ptr(ids), res,
                                         re.ctypes.data_as(C.POINTER(C.c_float)) if per_run else None,
                                         rg.ctypes.data_as(C.POINTER(C.c_float)) if per_run else None))
+        return self._results(res, n, re, rg, per_run)
+
+    def ad_dock_select(self, batch, lig_idx, params: DockParams, seed: int, per_run=False):
+        idx = _np(lig_idx, np.int32)
+        n = len(idx)
+        res = (DockResult * max(1, n))()
+        re = np.empty((n, params.nrun), np.float32) if per_run else None
+        rg = np.empty((n, params.nrun, STRIDE), np.float32) if per_run else None
+        self._check(lib().ad_dock_select(self.h, batch.h, n, _ptr(idx), C.byref(params), seed, res,
+                                         re.ctypes.data_as(C.POINTER(C.c_float)) if per_run else None,
+                                         rg.ctypes.data_as(C.POINTER(C.c_float)) if per_run else None))
+        return self._results(res, n, re, rg, per_run)
+
+    @staticmethod
+    def _results(res, n, re, rg, per_run):
         out = dict(best_energy=np.array([res[i].best_energy for i in range(n)], np.float32),
                    best_score=np.array([res[i].best_score for i in range(n)], np.float32),
                    best_genotype=np.array([list(res[i].best_genotype) for i in range(n)], np.float32),

@@ -163,6 +163,9 @@ extern "C" void ad_destroy(ad_ctx *c) {
     if (c->scratch[s]) hipFree(c->scratch[s]);
   c->free_dock_buffers();
   if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
+  if (c->aux_stream) hipStreamDestroy(c->aux_stream);
+  if (c->ev_fork) hipEventDestroy(c->ev_fork);
+  if (c->ev_join) hipEventDestroy(c->ev_join);
   delete c;
 }
 
@@ -338,6 +341,7 @@ extern "C" int ad_load_ligands(ad_ctx *c, int n, const ad_ligand *ligs, ad_batch
   }
   ad_batch *b = new ad_batch();
   b->ctx = c;
+  b->uid = c->next_batch_uid++;
   b->device = c->device;
   b->n_lig = n;
   std::vector<LigDesc> lig(n);

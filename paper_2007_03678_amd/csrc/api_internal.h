@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <map>
 #include <string>
 #include <vector>
 
@@ -37,8 +38,11 @@ struct DockArgs {
   float *energy;
   unsigned long long *evals;
   const int *run_order;
-  const uint32_t *lig_id;
+  const uint32_t *lig_id;   // random-stream id of each docked ligand
+  const int *lig_map;       // batch index of each docked ligand (null: identity)
   int n_runs, nrun, pop, n_ls, ls_iters;
+  int n_launch;      // runs covered by a launch: run_order[0..n_launch)
+  int stage_pairs;   // local search: pair records staged in LDS per ligand (0: none)
   uint32_t k0, k1;
   double cx_rate, mut_rate, tour_p, rho, eps, mut_t, mut_theta, mut_rot;
 };
@@ -46,6 +50,7 @@ struct DockArgs {
 hipError_t launch_dock_init(const EvalConst &C, int cap, const DockArgs &D, hipStream_t s);
 hipError_t launch_ga_generation(const EvalConst &C, int cap, const DockArgs &D, int gen, hipStream_t s);
 hipError_t launch_ls_generation(const EvalConst &C, int cap, const DockArgs &D, int gen, hipStream_t s);
+size_t ls_dynamic_lds(const EvalConst &C, const DockArgs &D);
 hipError_t launch_dock_finalize(const DockArgs &D, int buf, float *best_E, float *best_G, hipStream_t s);
 hipError_t launch_init_genotypes(const GridArgs &G, int n_tor, uint32_t k0, uint32_t k1, uint32_t lig_id, int run,
                                  int pop, float *out, hipStream_t s);
@@ -60,6 +65,7 @@ hipError_t launch_relayout(const float *soa, float *out4, size_t nn, int n_maps,
 
 struct ad_batch {
   ad_ctx *ctx = nullptr;
+  uint64_t uid = 0;   // unique per context (keys the autotuner's cache)
   int device = 0;
   int n_lig = 0;
   int cap = 64;   // atom capacity of the kernels that serve this batch (64 or 128)
@@ -110,6 +116,18 @@ struct ad_ctx {
   // docking state buffers
   void *dock_buf = nullptr;
   size_t dock_bytes = 0;
+  // docking schedule: hipGraph replay of the generation loop, autotuned LDS
+  // pair staging per atom-capacity bucket (or a forced value), and a second
+  // stream so the two buckets' launches overlap
+  bool use_graph = true;
+  bool autotune = true;
+  int forced_stage = -1;
+  hipStream_t aux_stream = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  std::map<std::vector<int64_t>, int> tune_cache;
+  int last_stage[2] = {-1, -1};
+  int last_graph = 0;
+  uint64_t next_batch_uid = 1;
   std::string err;
 
   int fail(int code, const std::string &msg);

@@ -59,10 +59,128 @@ int generations(const ad_dock_params *p, int n_ls) {
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+int ensure_aux(ad_ctx *c) {
+  if (c->aux_stream) return AD_OK;
+  if (hipStreamCreateWithFlags(&c->aux_stream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess)
+    return c->fail(AD_E_HIP, "cannot create the auxiliary stream");
+  return AD_OK;
+}
+
+// LDS pair-staging candidates of the local-search kernel, within the
+// work-group's LDS budget
+std::vector<int> stage_candidates(const EvalConst &C, const DockArgs &D, int cap, int max_pairs) {
+  const size_t static_lds = cap <= 64 ? 7 * 1024 : 14 * 1024;
+  std::vector<int> out = {0};
+  for (int ns : {128, 256, 512, 1024, 2048}) {
+    DockArgs t = D;
+    t.stage_pairs = ns;
+    if (static_lds + ls_dynamic_lds(C, t) > 64 * 1024) break;
+    out.push_back(ns);
+    if (ns >= max_pairs) break;   // every pair of the bucket already staged
+  }
+  return out;
+}
+
+// The pair-staging size of one bucket's local-search launches: forced, from
+// the cache, or timed.  Timing runs the bucket's local search (few
+// iterations) from the evaluated initial population on a copy of the
+// population buffers, once per candidate, on a strided sample of its runs;
+// the docking state itself is not touched.  Every candidate computes the
+// same values, so the choice affects speed only.
+int choose_stage(ad_ctx *c, const ad_batch *b, const int *sel, int n_lig, const EvalConst &C, const DockArgs &Dk,
+                 int cap, int max_pairs, int *out) {
+  const std::vector<int> cand = stage_candidates(C, Dk, cap, max_pairs);
+  if (c->forced_stage >= 0) {
+    int pick = 0;
+    for (int ns : cand)
+      if (ns <= c->forced_stage) pick = ns;
+    *out = pick;
+    return AD_OK;
+  }
+  if (!c->autotune || cand.size() < 2) {
+    *out = 0;
+    return AD_OK;
+  }
+  std::vector<int64_t> key = {(int64_t)b->uid, cap, Dk.pop, Dk.n_ls, Dk.n_launch, n_lig};
+  if (sel) {
+    uint64_t h = 1469598103934665603ull;
+    for (int l = 0; l < n_lig; ++l) h = (h ^ (uint64_t)sel[l]) * 1099511628211ull;
+    key.push_back((int64_t)h);
+  }
+  auto it = c->tune_cache.find(key);
+  if (it != c->tune_cache.end()) {
+    *out = it->second;
+    return AD_OK;
+  }
+  const int K = std::min(Dk.n_launch, std::max(1, 3072 / std::max(1, Dk.n_ls)) * 2);
+  const size_t pop_floats = (size_t)Dk.n_runs * Dk.pop;
+  const size_t sz_g = align256(pop_floats * kStride * sizeof(float));
+  const size_t sz_e = align256(pop_floats * sizeof(float));
+  const size_t sz_v = align256((size_t)Dk.n_runs * sizeof(unsigned long long));
+  const size_t sz_o = align256((size_t)K * sizeof(int));
+  char *blk = (char *)c->scratch_alloc(sz_g + sz_e + sz_v + sz_o, 3);
+  if (!blk) return c->fail(AD_E_OOM, "cannot allocate autotuning buffers");
+  std::vector<int> host_order(Dk.n_launch), sample(K);
+  HIP_TRY(c, hipMemcpyAsync(host_order.data(), Dk.run_order, Dk.n_launch * sizeof(int), hipMemcpyDeviceToHost,
+                            c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  for (int k = 0; k < K; ++k) sample[k] = host_order[(size_t)k * Dk.n_launch / K];
+  DockArgs T = Dk;
+  T.geno = (float *)blk;
+  T.energy = (float *)(blk + sz_g);
+  T.evals = (unsigned long long *)(blk + sz_g + sz_e);
+  int *d_sample = (int *)(blk + sz_g + sz_e + sz_v);
+  T.run_order = d_sample;
+  T.n_launch = K;
+  T.ls_iters = std::min(Dk.ls_iters, 24);
+  HIP_TRY(c, hipMemcpyAsync(d_sample, sample.data(), K * sizeof(int), hipMemcpyHostToDevice, c->stream));
+  hipEvent_t e0, e1;
+  HIP_TRY(c, hipEventCreate(&e0));
+  HIP_TRY(c, hipEventCreate(&e1));
+  int best = 0;
+  float best_ms = INFINITY;
+  int rc = AD_OK;
+  for (int ns : cand) {
+    T.stage_pairs = ns;
+    float ms_min = INFINITY;
+    for (int rep = 0; rep < 3 && rc == AD_OK; ++rep) {
+      hipError_t e = hipMemcpyAsync(T.geno, Dk.geno, pop_floats * kStride * sizeof(float), hipMemcpyDeviceToDevice,
+                                    c->stream);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(T.energy, Dk.energy, pop_floats * sizeof(float), hipMemcpyDeviceToDevice, c->stream);
+      if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+      if (e == hipSuccess) e = launch_ls_generation(C, cap, T, 0, c->stream);
+      if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) rc = c->hip_fail(e, "autotuning launch");
+      ms_min = std::min(ms_min, ms);
+    }
+    if (rc) break;
+    // a larger staging size must win by 3 % (timing noise and the LDS it
+    // takes from co-resident work-groups of other launches)
+    if (ms_min < 0.97f * best_ms) {
+      best_ms = ms_min;
+      best = ns;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc) return rc;
+  c->tune_cache[key] = best;
+  *out = best;
+  return AD_OK;
+}
+
 }  // namespace
 
-extern "C" int ad_dock_batch(ad_ctx *c, const ad_batch *b, const ad_dock_params *p, uint64_t seed,
-                             const uint32_t *lig_ids, ad_dock_result *out, float *run_energy, float *run_genotype) {
+// Docks n_lig ligands of batch b: sel[l] is the batch index of the l-th
+// (null: 0..n_lig-1); ids[l] its random-stream id (null: the batch index).
+int dock_impl(ad_ctx *c, const ad_batch *b, int n_lig, const int *sel, const ad_dock_params *p, uint64_t seed,
+              const uint32_t *lig_ids, ad_dock_result *out, float *run_energy, float *run_genotype) {
   if (!c) return AD_E_INVALID;
   if (!b) return c->fail(AD_E_INVALID, "null batch");
   if (b->ctx != c) return c->fail(AD_E_INVALID, "batch belongs to another context");
@@ -72,9 +190,16 @@ extern "C" int ad_dock_batch(ad_ctx *c, const ad_batch *b, const ad_dock_params 
       return c->fail(AD_E_STATE, "grid maps changed since the batch was loaded; reload the ligands");
   int rc = check_params(c, p);
   if (rc) return rc;
-  if (!out) return c->fail(AD_E_INVALID, "null result array");
-  const int n_lig = b->n_lig;
+  if (n_lig < 0) return c->fail(AD_E_INVALID, "n < 0");
   if (n_lig == 0) return AD_OK;
+  if (!out) return c->fail(AD_E_INVALID, "null result array");
+  if (sel)
+    for (int l = 0; l < n_lig; ++l)
+      if (sel[l] < 0 || sel[l] >= b->n_lig) return c->fail(AD_E_INVALID, "ligand index out of range");
+  auto bidx = [&](int l) { return sel ? sel[l] : l; };
+  int cap = 64;
+  for (int l = 0; l < n_lig; ++l)
+    if (b->lig_host[bidx(l)].n_atoms > 64) cap = 128;
   if ((int64_t)n_lig * p->nrun * p->pop > (int64_t)1 << 31)
     return c->fail(AD_E_INVALID, "n_lig * nrun * pop too large for one batch");
   const int n_runs = n_lig * p->nrun;
@@ -93,7 +218,9 @@ extern "C" int ad_dock_batch(ad_ctx *c, const ad_batch *b, const ad_dock_params 
   const size_t sz_lE = align256((size_t)n_lig * sizeof(float));
   const size_t sz_lT = align256((size_t)n_lig * 3 * sizeof(float));
   const size_t sz_li = align256((size_t)n_lig * sizeof(int));
-  const size_t total = sz_geno + sz_E + sz_ev + sz_ord + sz_id + sz_bE + sz_bG + sz_lG + sz_lE + sz_lT + sz_li;
+  const size_t sz_map = sel ? align256((size_t)n_lig * sizeof(int)) : 0;
+  const size_t total =
+      sz_geno + sz_E + sz_ev + sz_ord + sz_id + sz_bE + sz_bG + sz_lG + sz_lE + sz_lT + sz_li + sz_map;
   hipSetDevice(c->device);
   if (c->dock_bytes < total) {
     hipStreamSynchronize(c->stream);
@@ -120,8 +247,10 @@ extern "C" int ad_dock_batch(ad_ctx *c, const ad_batch *b, const ad_dock_params 
   float *d_lE = (float *)carve(sz_lE);
   float *d_lT = (float *)carve(sz_lT);
   int *d_li = (int *)carve(sz_li);
+  int *d_map = sel ? (int *)carve(sz_map) : nullptr;
   D.run_order = d_order;
   D.lig_id = d_id;
+  D.lig_map = d_map;
   D.n_runs = n_runs;
   D.nrun = p->nrun;
   D.pop = p->pop;
@@ -138,36 +267,120 @@ extern "C" int ad_dock_batch(ad_ctx *c, const ad_batch *b, const ad_dock_params 
   D.mut_theta = p->mut_theta;
   D.mut_rot = p->mut_rot;
 
-  // runs of expensive ligands first, so the last work-groups of each launch
-  // are the cheap ones (longest-processing-time order)
-  std::vector<int> order(n_runs);
-  std::iota(order.begin(), order.end(), 0);
+  // runs grouped by kernel atom capacity (bucket 0: <= 64 atoms, bucket 1:
+  // <= 128), each bucket in longest-processing-time order so the last
+  // work-groups of every launch are the cheap ones
   std::vector<double> cost(n_lig);
-  for (int l = 0; l < n_lig; ++l)
-    cost[l] = b->lig_host[l].n_pairs + 4.0 * b->lig_host[l].n_atoms + 2.0 * b->lig_host[l].n_tor;
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int x, int y) { return cost[x / p->nrun] > cost[y / p->nrun]; });
+  std::vector<int> bucket_of(n_lig);
+  for (int l = 0; l < n_lig; ++l) {
+    const LigDesc &d = b->lig_host[bidx(l)];
+    cost[l] = d.n_pairs + 4.0 * d.n_atoms + 2.0 * d.n_tor;
+    bucket_of[l] = d.n_atoms > 64 ? 1 : 0;
+  }
+  std::vector<int> order;
+  order.reserve(n_runs);
+  int bstart[3] = {0, 0, n_runs};
+  for (int bk = 0; bk < 2; ++bk) {
+    bstart[bk] = (int)order.size();
+    for (int R = 0; R < n_runs; ++R)
+      if (bucket_of[R / p->nrun] == bk) order.push_back(R);
+    std::stable_sort(order.begin() + bstart[bk], order.end(),
+                     [&](int x, int y) { return cost[x / p->nrun] > cost[y / p->nrun]; });
+  }
   std::vector<uint32_t> ids(n_lig);
-  for (int l = 0; l < n_lig; ++l) ids[l] = lig_ids ? lig_ids[l] : (uint32_t)l;
+  for (int l = 0; l < n_lig; ++l) ids[l] = lig_ids ? lig_ids[l] : (uint32_t)bidx(l);
   HIP_TRY(c, hipMemcpyAsync(d_order, order.data(), n_runs * sizeof(int), hipMemcpyHostToDevice, c->stream));
+  if (sel) HIP_TRY(c, hipMemcpyAsync(d_map, sel, n_lig * sizeof(int), hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipMemcpyAsync(d_id, ids.data(), n_lig * sizeof(uint32_t), hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipMemsetAsync(D.evals, 0, (size_t)n_runs * sizeof(unsigned long long), c->stream));
 
   const EvalConst C = c->eval_const(b);
+  DockArgs Db[2];
+  int max_pairs[2] = {0, 0};
+  for (int l = 0; l < n_lig; ++l)
+    max_pairs[bucket_of[l]] = std::max(max_pairs[bucket_of[l]], b->lig_host[bidx(l)].n_pairs);
+  int n_buckets = 0;
+  for (int bk = 0; bk < 2; ++bk) {
+    Db[bk] = D;
+    Db[bk].run_order = d_order + bstart[bk];
+    Db[bk].n_launch = bstart[bk + 1] - bstart[bk];
+    Db[bk].stage_pairs = 0;
+    n_buckets += Db[bk].n_launch > 0;
+  }
   {
     const int t0 = c->timing_begin(0);
-    HIP_TRY(c, launch_dock_init(C, b->cap, D, c->stream));
+    for (int bk = 0; bk < 2; ++bk) HIP_TRY(c, launch_dock_init(C, bk ? 128 : 64, Db[bk], c->stream));
     c->timing_end(0, t0);
   }
-  for (int gen = 1; gen <= G; ++gen) {
-    const int t1 = c->timing_begin(1);
-    HIP_TRY(c, launch_ga_generation(C, b->cap, D, gen, c->stream));
-    c->timing_end(1, t1);
-    if (n_ls > 0 && p->ls_iters > 0) {
-      const int t2 = c->timing_begin(2);
-      HIP_TRY(c, launch_ls_generation(C, b->cap, D, gen, c->stream));
-      c->timing_end(2, t2);
+  const bool do_ls = n_ls > 0 && p->ls_iters > 0;
+  for (int bk = 0; bk < 2; ++bk) {
+    c->last_stage[bk] = -1;
+    if (!Db[bk].n_launch || !do_ls) continue;
+    int st = 0;
+    rc = choose_stage(c, b, sel, n_lig, C, Db[bk], bk ? 128 : 64, max_pairs[bk], &st);
+    if (rc) return rc;
+    Db[bk].stage_pairs = st;
+    c->last_stage[bk] = st;
+  }
+
+  // the generation loop: bucket 0 on the context's stream, bucket 1 on the
+  // auxiliary stream.  Eager with kernel timing (phases forked and joined
+  // so each phase is timed on the context's stream); otherwise captured once
+  // into a graph whose two bucket chains run independently, and replayed.
+  if (n_buckets == 2) {
+    rc = ensure_aux(c);
+    if (rc) return rc;
+  }
+  hipStream_t bs[2] = {c->stream, n_buckets == 2 ? c->aux_stream : c->stream};
+  auto fork = [&]() -> hipError_t {
+    if (n_buckets < 2) return hipSuccess;
+    hipError_t e = hipEventRecord(c->ev_fork, c->stream);
+    return e != hipSuccess ? e : hipStreamWaitEvent(c->aux_stream, c->ev_fork, 0);
+  };
+  auto join = [&]() -> hipError_t {
+    if (n_buckets < 2) return hipSuccess;
+    hipError_t e = hipEventRecord(c->ev_join, c->aux_stream);
+    return e != hipSuccess ? e : hipStreamWaitEvent(c->stream, c->ev_join, 0);
+  };
+  const bool graph = c->use_graph && !c->timing && G > 0;
+  c->last_graph = graph ? 1 : 0;
+  if (!graph) {
+    for (int gen = 1; gen <= G; ++gen) {
+      const int t1 = c->timing_begin(1);
+      HIP_TRY(c, fork());
+      for (int bk = 0; bk < 2; ++bk) HIP_TRY(c, launch_ga_generation(C, bk ? 128 : 64, Db[bk], gen, bs[bk]));
+      HIP_TRY(c, join());
+      c->timing_end(1, t1);
+      if (do_ls) {
+        const int t2 = c->timing_begin(2);
+        HIP_TRY(c, fork());
+        for (int bk = 0; bk < 2; ++bk) HIP_TRY(c, launch_ls_generation(C, bk ? 128 : 64, Db[bk], gen, bs[bk]));
+        HIP_TRY(c, join());
+        c->timing_end(2, t2);
+      }
     }
+  } else {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = fork();
+    for (int gen = 1; gen <= G && e == hipSuccess; ++gen)
+      for (int bk = 0; bk < 2 && e == hipSuccess; ++bk) {
+        e = launch_ga_generation(C, bk ? 128 : 64, Db[bk], gen, bs[bk]);
+        if (e == hipSuccess && do_ls) e = launch_ls_generation(C, bk ? 128 : 64, Db[bk], gen, bs[bk]);
+      }
+    if (e == hipSuccess) e = join();
+    const hipError_t e_end = hipStreamEndCapture(c->stream, &g);
+    if (e != hipSuccess || e_end != hipSuccess) {
+      if (g) hipGraphDestroy(g);
+      return c->hip_fail(e != hipSuccess ? e : e_end, "capture of the generation loop");
+    }
+    e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    if (e == hipSuccess) e = hipGraphLaunch(ge, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (ge) hipGraphExecDestroy(ge);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) return c->hip_fail(e, "generation-loop graph");
   }
   HIP_TRY(c, launch_dock_finalize(D, G & 1, d_bE, d_bG, c->stream));
 
@@ -192,12 +405,12 @@ extern "C" int ad_dock_batch(ad_ctx *c, const ad_batch *b, const ad_dock_params 
       if (e < eb || (std::isnan(eb) && !std::isnan(e))) br = r;
     }
     best_run[l] = br;
-    lidx[l] = l;
+    lidx[l] = bidx(l);
     memcpy(&lG[(size_t)l * kStride], &bG[(size_t)(l * p->nrun + br) * kStride], kStride * sizeof(float));
   }
   HIP_TRY(c, hipMemcpyAsync(d_lG, lG.data(), lG.size() * sizeof(float), hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipMemcpyAsync(d_li, lidx.data(), n_lig * sizeof(int), hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(c, launch_score(C, b->cap, n_lig, d_li, d_lG, d_lE, nullptr, d_lT, c->stream));
+  HIP_TRY(c, launch_score(C, cap, n_lig, d_li, d_lG, d_lE, nullptr, d_lT, c->stream));
   std::vector<float> lT((size_t)n_lig * 3);
   HIP_TRY(c, hipMemcpyAsync(lT.data(), d_lT, lT.size() * sizeof(float), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -216,6 +429,38 @@ extern "C" int ad_dock_batch(ad_ctx *c, const ad_batch *b, const ad_dock_params 
   }
   if (run_energy) memcpy(run_energy, bE.data(), n_runs * sizeof(float));
   if (run_genotype) memcpy(run_genotype, bG.data(), (size_t)n_runs * kStride * sizeof(float));
+  return AD_OK;
+}
+
+extern "C" int ad_dock_batch(ad_ctx *c, const ad_batch *b, const ad_dock_params *p, uint64_t seed,
+                             const uint32_t *lig_ids, ad_dock_result *out, float *run_energy, float *run_genotype) {
+  if (!c) return AD_E_INVALID;
+  if (!b) return c->fail(AD_E_INVALID, "null batch");
+  return dock_impl(c, b, b->n_lig, nullptr, p, seed, lig_ids, out, run_energy, run_genotype);
+}
+
+extern "C" int ad_dock_select(ad_ctx *c, const ad_batch *b, int n, const int *lig_idx, const ad_dock_params *p,
+                              uint64_t seed, ad_dock_result *out, float *run_energy, float *run_genotype) {
+  if (!c) return AD_E_INVALID;
+  if (n > 0 && !lig_idx) return c->fail(AD_E_INVALID, "null ligand index list");
+  return dock_impl(c, b, n, lig_idx, p, seed, nullptr, out, run_energy, run_genotype);
+}
+
+extern "C" int ad_set_schedule(ad_ctx *c, int use_graph, int autotune, int stage_pairs) {
+  if (!c) return AD_E_INVALID;
+  c->use_graph = use_graph != 0;
+  c->autotune = autotune != 0;
+  c->forced_stage = stage_pairs < 0 ? -1 : stage_pairs;
+  return AD_OK;
+}
+
+extern "C" int ad_get_schedule(ad_ctx *c, int *stage_pairs, int *graph_used) {
+  if (!c) return AD_E_INVALID;
+  if (stage_pairs) {
+    stage_pairs[0] = c->last_stage[0];
+    stage_pairs[1] = c->last_stage[1];
+  }
+  if (graph_used) *graph_used = c->last_graph;
   return AD_OK;
 }
 

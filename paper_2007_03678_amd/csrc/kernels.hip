@@ -309,9 +309,16 @@ __device__ __forceinline__ void rot_matrix(const double u[3], double c, double s
 // Evaluate the genotype in S.geno.  Returns the total energy (every lane);
 // with GRAD the gradient is written to S.grad[0..39]; terms (lane 0) gets
 // {inter, intra}.  Ends with the LDS in a consistent state (barrier).
-template <int CAP, bool GRAD>
+// Pairs staged in LDS by a local search (see k_ls_generation): the first `n`
+// pair records of the ligand and the whole type-pair table, at byte offset
+// `off` of the work-group's dynamic LDS.
+struct PairStage {
+  int off, n;
+};
+
+template <int CAP, bool GRAD, bool STAGE = false>
 __device__ double evaluate(const EvalConst &C, const LaneLig<CAP> &LL, EvalLds<CAP> &S, int lane, double *inter_out,
-                           double *intra_out) {
+                           double *intra_out, PairStage st = PairStage{0, 0}) {
   constexpr int APL = CAP / 64;
   const LigDesc &L = LL.L;
   // keep the ligand records below from being hoisted out of a caller's loop
@@ -385,10 +392,20 @@ __device__ double evaluate(const EvalConst &C, const LaneLig<CAP> &LL, EvalLds<C
   double e_intra = 0.0;
   const PairRec *pr = C.batch.pairs + L.pair_off;
   const LJRec *ljt = C.batch.lj;
+  extern __shared__ __attribute__((aligned(16))) char dyn_lds[];
+  const LJRec *s_lj = reinterpret_cast<const LJRec *>(dyn_lds + st.off);
+  const PairRec *s_pr = reinterpret_cast<const PairRec *>(dyn_lds + st.off + C.ff.n_types * C.ff.n_types * 16);
   for (int p = lane; p < L.n_pairs; p += 64) {
-    const PairRec rec = pr[p];
-    const int i = rec.ijt & 0xff, j = (rec.ijt >> 8) & 0xff, tp = rec.ijt >> 16;
-    const LJRec lj = ljt[tp];
+    PairRec rec;
+    LJRec lj;
+    if (STAGE && p < st.n) {
+      rec = s_pr[p];
+      lj = s_lj[rec.ijt >> 16];
+    } else {
+      rec = pr[p];
+      lj = STAGE ? s_lj[rec.ijt >> 16] : ljt[rec.ijt >> 16];
+    }
+    const int i = rec.ijt & 0xff, j = (rec.ijt >> 8) & 0xff;
     const double dx = S.x[i][0] - S.x[j][0], dy = S.x[i][1] - S.x[j][1], dz = S.x[i][2] - S.x[j][2];
     const float r2 = (float)(dx * dx + dy * dy + dz * dz);
     float fs;
@@ -514,9 +531,9 @@ __global__ __launch_bounds__(64) void k_score(EvalConst C, int n, const int *__r
 // Degrees of freedom on lanes: 0-2 translation, 3-5 rotation vector,
 // 7..7+T-1 torsions (lane 6 is the fourth quaternion slot).
 // ---------------------------------------------------------------------------
-template <int CAP>
+template <int CAP, bool STAGE = false>
 __device__ void adadelta_wave(const EvalConst &C, const LaneLig<CAP> &LL, EvalLds<CAP> &S, int lane, float *geno_io,
-                              float *E_io, int iters, double rho_d, double eps_d) {
+                              float *E_io, int iters, double rho_d, double eps_d, PairStage st = PairStage{0, 0}) {
   const int T = LL.L.n_tor;
   // genes are FP32 values; the step arithmetic runs in FP32 with native
   // square roots (the accumulated squared gradient in FP64: gradients of
@@ -531,7 +548,7 @@ __device__ void adadelta_wave(const EvalConst &C, const LaneLig<CAP> &LL, EvalLd
   for (int it = 0; it < iters; ++it) {
     if (lane < kStride) S.geno[lane] = (double)gene;
     __syncthreads();
-    const double E = evaluate<CAP, true>(C, LL, S, lane, nullptr, nullptr);
+    const double E = evaluate<CAP, true, STAGE>(C, LL, S, lane, nullptr, nullptr, st);
     const double gd = dof ? S.grad[lane] : 0.0;
     if (E < best_E) {
       best_E = E;
@@ -599,6 +616,9 @@ __device__ __forceinline__ size_t pop_off(const DockArgs &D, int buf, int R) {
 
 __device__ __forceinline__ float round_gene(double v) { return (float)v; }
 
+// byte offset of the staged pair area in k_ls_generation's dynamic LDS
+__host__ __device__ __forceinline__ int stage_offset(int pop) { return (pop * 4 + 15) & ~15; }
+
 // Draw the generation-0 individual `indiv` of (lig id, run): genes on lanes.
 __device__ double init_gene(const GridArgs &G, const Rng &rng, int indiv, int lane, int n_tor) {
   const double PI = 3.14159265358979323846;
@@ -632,7 +652,7 @@ __global__ __launch_bounds__(64) void k_init_pop(EvalConst C, DockArgs D) {
   const int i = blockIdx.x % D.pop;
   const int li = R / D.nrun, run = R % D.nrun;
   LaneLig<CAP> LL;
-  LL.load(C, li, lane);
+  LL.load(C, D.lig_map ? D.lig_map[li] : li, lane);
   const Rng rng{D.k0, D.k1, D.lig_id[li], (uint32_t)run, 0u};
   const float g = round_gene(init_gene(C.grid, rng, i, lane, LL.L.n_tor));
   if (lane < kStride) S.geno[lane] = (double)g;
@@ -700,7 +720,7 @@ __global__ __launch_bounds__(64) void k_ga_generation(EvalConst C, DockArgs D, i
     return;
   }
   LaneLig<CAP> LL;
-  LL.load(C, li, lane);
+  LL.load(C, D.lig_map ? D.lig_map[li] : li, lane);
   const int T = LL.L.n_tor;
   const Rng rng{D.k0, D.k1, D.lig_id[li], (uint32_t)run, (uint32_t)gen};
   const uint4 s0 = rng.block(i, kStSelect, 0), s1 = rng.block(i, kStSelect, 1);
@@ -756,10 +776,15 @@ __global__ __launch_bounds__(64) void k_ga_generation(EvalConst C, DockArgs D, i
 // ADADELTA on the individuals picked for generation `gen`: n_ls distinct
 // indices from 1..pop-1 by a partial Fisher-Yates shuffle (word s of the
 // pick stream draws the partner of position s).  Dynamic LDS: pop ints.
-template <int CAP>
+// With STAGE the first D.stage_pairs pair records of the ligand and the
+// type-pair table are copied to LDS once and read from there by all
+// ls_iters evaluations (the results are bitwise the same either way).
+// Dynamic LDS: pop ints (the pick permutation), then the staged records.
+template <int CAP, bool STAGE>
 __global__ __launch_bounds__(64) void k_ls_generation(EvalConst C, DockArgs D, int gen) {
   __shared__ EvalLds<CAP> S;
-  extern __shared__ int perm[];
+  extern __shared__ __attribute__((aligned(16))) char dyn_lds[];
+  int *perm = reinterpret_cast<int *>(dyn_lds);
   const int lane = threadIdx.x;
   const int R = D.run_order[blockIdx.x / D.n_ls];
   const int slot = blockIdx.x % D.n_ls;
@@ -779,9 +804,21 @@ __global__ __launch_bounds__(64) void k_ls_generation(EvalConst C, DockArgs D, i
   __syncthreads();
   const int indiv = perm[slot];
   LaneLig<CAP> LL;
-  LL.load(C, li, lane);
+  LL.load(C, D.lig_map ? D.lig_map[li] : li, lane);
+  PairStage st{0, 0};
+  if (STAGE) {
+    st.off = stage_offset(D.pop);
+    st.n = min(LL.L.n_pairs, D.stage_pairs);
+    const int ntt = C.ff.n_types * C.ff.n_types;
+    LJRec *s_lj = reinterpret_cast<LJRec *>(dyn_lds + st.off);
+    PairRec *s_pr = reinterpret_cast<PairRec *>(dyn_lds + st.off + ntt * 16);
+    for (int k = lane; k < ntt; k += 64) s_lj[k] = C.batch.lj[k];
+    const PairRec *src = C.batch.pairs + LL.L.pair_off;
+    for (int k = lane; k < st.n; k += 64) s_pr[k] = src[k];
+    __syncthreads();
+  }
   const size_t off = pop_off(D, gen & 1, R) + indiv;
-  adadelta_wave<CAP>(C, LL, S, lane, D.geno + off * kStride, D.energy + off, D.ls_iters, D.rho, D.eps);
+  adadelta_wave<CAP, STAGE>(C, LL, S, lane, D.geno + off * kStride, D.energy + off, D.ls_iters, D.rho, D.eps, st);
   if (lane == 0) atomicAdd(&D.evals[R], (unsigned long long)D.ls_iters);
 }
 
@@ -930,25 +967,39 @@ hipError_t launch_relayout(const float *soa, float *out4, size_t nn, int n_maps,
 
 
 hipError_t launch_dock_init(const EvalConst &C, int cap, const DockArgs &D, hipStream_t s) {
-  dim3 grid((unsigned)D.n_runs * D.pop), block(64);
+  if (D.n_launch <= 0) return hipSuccess;
+  dim3 grid((unsigned)D.n_launch * D.pop), block(64);
   if (cap <= 64) hipLaunchKernelGGL((k_init_pop<64>), grid, block, 0, s, C, D);
   else hipLaunchKernelGGL((k_init_pop<128>), grid, block, 0, s, C, D);
   return hipGetLastError();
 }
 
 hipError_t launch_ga_generation(const EvalConst &C, int cap, const DockArgs &D, int gen, hipStream_t s) {
-  dim3 grid((unsigned)D.n_runs * D.pop), block(64);
+  if (D.n_launch <= 0) return hipSuccess;
+  dim3 grid((unsigned)D.n_launch * D.pop), block(64);
   if (cap <= 64) hipLaunchKernelGGL((k_ga_generation<64>), grid, block, 0, s, C, D, gen);
   else hipLaunchKernelGGL((k_ga_generation<128>), grid, block, 0, s, C, D, gen);
   return hipGetLastError();
 }
 
+size_t ls_dynamic_lds(const EvalConst &C, const DockArgs &D) {
+  if (D.stage_pairs <= 0) return (size_t)D.pop * sizeof(int);
+  return (size_t)stage_offset(D.pop) + (size_t)C.ff.n_types * C.ff.n_types * 16 + (size_t)D.stage_pairs * 16;
+}
+
 hipError_t launch_ls_generation(const EvalConst &C, int cap, const DockArgs &D, int gen, hipStream_t s) {
+  if (D.n_launch <= 0 || D.n_ls <= 0) return hipSuccess;
   dim3 block(64);
-  dim3 lgrid((unsigned)D.n_runs * D.n_ls);
-  size_t dyn = (size_t)D.pop * sizeof(int);
-  if (cap <= 64) hipLaunchKernelGGL((k_ls_generation<64>), lgrid, block, dyn, s, C, D, gen);
-  else hipLaunchKernelGGL((k_ls_generation<128>), lgrid, block, dyn, s, C, D, gen);
+  dim3 lgrid((unsigned)D.n_launch * D.n_ls);
+  const size_t dyn = ls_dynamic_lds(C, D);
+  const bool st = D.stage_pairs > 0;
+  if (cap <= 64) {
+    if (st) hipLaunchKernelGGL((k_ls_generation<64, true>), lgrid, block, dyn, s, C, D, gen);
+    else hipLaunchKernelGGL((k_ls_generation<64, false>), lgrid, block, dyn, s, C, D, gen);
+  } else {
+    if (st) hipLaunchKernelGGL((k_ls_generation<128, true>), lgrid, block, dyn, s, C, D, gen);
+    else hipLaunchKernelGGL((k_ls_generation<128, false>), lgrid, block, dyn, s, C, D, gen);
+  }
   return hipGetLastError();
 }
 

@@ -130,6 +130,15 @@ def test_dock_accounting_rescoring_and_reproducibility(pkg, setup, orc):
     solo = ctx.ad_load_ligands([ligs[2]])
     r3 = ctx.ad_dock_batch(solo, p, seed, lig_ids=np.array([2], np.uint32), per_run=True)
     assert np.array_equal(r3["run_energy"][0], r["run_energy"][2])
+    # docking a subset of the batch (the screened path) gives the same results
+    r5 = ctx.ad_dock_select(batch, np.array([2, 0], np.int32), p, seed, per_run=True)
+    assert np.array_equal(r5["run_energy"], r["run_energy"][[2, 0]])
+    assert np.array_equal(r5["best_genotype"], r["best_genotype"][[2, 0]])
+    assert np.array_equal(r5["best_score"], r["best_score"][[2, 0]])
+    assert np.all(r5["evals"] == r["evals"][[2, 0]])
+    with pytest.raises(pkg.AddockError):
+        ctx.ad_dock_select(batch, np.array([4], np.int32), p, seed)
+    assert len(ctx.ad_dock_select(batch, np.zeros(0, np.int32), p, seed)["best_energy"]) == 0
     r4 = ctx.ad_dock_batch(batch, p, seed + 1, per_run=True)
     assert not np.array_equal(r4["run_energy"], r["run_energy"])
     # the search improves on the initial population
@@ -140,6 +149,44 @@ def test_dock_accounting_rescoring_and_reproducibility(pkg, setup, orc):
     assert np.mean(r["run_energy"] < init - 1.0) > 0.5
     solo.free()
     batch.free()
+
+
+def test_schedules_give_identical_results(pkg, setup):
+    """Both atom-capacity buckets, eager and graph replay, forced and
+    autotuned LDS pair staging: bitwise the same docking results."""
+    ctx, grid, G = setup
+    ligs = [synth.ligand(70 + i, n, t) for i, (n, t) in enumerate([(12, 2), (30, 7), (70, 20), (50, 12), (90, 25)])]
+    batch = ctx.ad_load_ligands(ligs)
+    p = small_params(pkg, ls_iters=30, max_gens=5)
+    ref = None
+    try:
+        for use_graph, autotune, stage in [(False, False, 0), (True, False, 0), (False, False, 2048),
+                                           (True, False, 256), (True, True, -1), (True, True, -1)]:
+            ctx.ad_set_schedule(use_graph, autotune, stage)
+            r = ctx.ad_dock_batch(batch, p, 77, per_run=True)
+            info = ctx.ad_get_schedule()
+            assert info["graph"] == use_graph
+            assert info["stage_pairs"][0] >= 0 and info["stage_pairs"][1] >= 0   # both buckets used
+            if stage == 0:
+                assert info["stage_pairs"] == [0, 0]
+            if ref is None:
+                ref = r
+                continue
+            for k in ("run_energy", "run_genotype", "evals", "best_score"):
+                assert np.array_equal(r[k], ref[k]), (use_graph, autotune, stage, k)
+        # kernel timing runs the loop eagerly, with the same results
+        ctx.ad_set_kernel_timing(True)
+        r = ctx.ad_dock_batch(batch, p, 77, per_run=True)
+        ctx.ad_set_kernel_timing(False)
+        assert not ctx.ad_get_schedule()["graph"]
+        assert np.array_equal(r["run_energy"], ref["run_energy"])
+        # a subset that holds only the small bucket
+        r2 = ctx.ad_dock_select(batch, np.array([3, 0], np.int32), p, 77, per_run=True)
+        assert ctx.ad_get_schedule()["stage_pairs"][1] == -1
+        assert np.array_equal(r2["run_energy"], ref["run_energy"][[3, 0]])
+    finally:
+        ctx.ad_set_schedule()
+        batch.free()
 
 
 def test_dock_parameter_errors(pkg, setup):

@@ -88,3 +88,19 @@ def test_fast_ligand_type_frequencies():
     for name, p in synth.FREQ_SIX.items():
         # HD that finds no host becomes C, so allow a small shift between the two
         assert abs(f[synth.TYPE_ID[name]] - p) < (0.02 if name in ("C", "HD") else 0.01), name
+
+
+def test_screen_helpers():
+    from paper_2007_03678_amd import screen
+    judge = np.array([5.0, -3.0, 0.0, -9.0, 2.0, -1.0, 7.0, -4.0, 1.0, 3.0])
+    assert list(screen.top_fraction(judge, 0.2)) == [3, 7]
+    assert len(screen.top_fraction(judge, 0.25)) == 3
+    assert screen.recall(judge, [7, 3, 0], top_frac=0.2) == (2, 2)
+    assert screen.recall(judge, [7, 0], top_frac=0.2) == (1, 2)
+    # a perfect predictor needs exactly the top fraction; a reversed one needs all
+    assert screen.fraction_for_recall(judge, judge, 1.0, 0.2) == pytest.approx(0.2)
+    assert screen.fraction_for_recall(-judge, judge, 1.0, 0.2) == pytest.approx(1.0)
+    assert screen.fraction_for_recall(-judge, judge, 0.5, 0.2) == pytest.approx(0.9)
+    lo, hi = screen.clopper_pearson(19, 20)
+    assert lo == pytest.approx(0.7513, abs=1e-3) and hi == pytest.approx(0.9987, abs=1e-3)
+    assert screen.clopper_pearson(0, 10)[0] == 0.0 and screen.clopper_pearson(10, 10)[1] == 1.0
