@@ -41,12 +41,17 @@ class DockParams(C.Structure):
                 ("ls_rate", C.c_double), ("ls_iters", C.c_int), ("cx_rate", C.c_double),
                 ("mut_rate", C.c_double), ("tour_p", C.c_double), ("rho", C.c_double),
                 ("eps", C.c_double), ("mut_t", C.c_double), ("mut_theta", C.c_double),
-                ("mut_rot", C.c_double)]
+                ("mut_rot", C.c_double), ("ls_method", C.c_int), ("autostop", C.c_int),
+                ("sw_rho", C.c_double), ("sw_rho_lb", C.c_double), ("sw_max_succ", C.c_int),
+                ("sw_max_fail", C.c_int), ("sw_sigma_t", C.c_double), ("sw_sigma_ang", C.c_double),
+                ("stop_std", C.c_double)]
 
 
 DEFAULT_DOCK = dict(nrun=4, pop=50, max_gens=50, max_evals=10**12, ls_rate=0.06, ls_iters=300,
                     cx_rate=0.8, mut_rate=0.02, tour_p=0.6, rho=0.8, eps=1e-2, mut_t=2.0,
-                    mut_theta=np.pi / 2, mut_rot=np.pi / 2)
+                    mut_theta=np.pi / 2, mut_rot=np.pi / 2, ls_method=0, autostop=0,
+                    sw_rho=1.0, sw_rho_lb=0.01, sw_max_succ=4, sw_max_fail=4, sw_sigma_t=1.0,
+                    sw_sigma_ang=0.2, stop_std=0.15)
 
 
 def make_ff(ff: dict) -> FF:
@@ -123,6 +128,10 @@ def lib():
         L.orc_ls_pick.argtypes = [C.c_uint64, u32, u32, u32, C.c_int, C.c_int, ip]
         L.orc_adadelta.argtypes = [vp, vp, C.POINTER(DockParams), dp, C.c_int, dp, dp]
         L.orc_n_ls.argtypes = [C.POINTER(DockParams)]
+        L.orc_solis_wets.argtypes = [vp, vp, C.POINTER(DockParams), dp, C.c_double, C.c_int, C.c_uint64, u32, u32,
+                                     u32, u32, dp, dp, ip]
+        L.orc_sw_deviate.argtypes = [C.c_uint64, u32, u32, u32, u32, u32, C.c_int]
+        L.orc_sw_deviate.restype = C.c_double
         L.orc_dock_run.argtypes = [vp, vp, C.POINTER(DockParams), C.c_uint64, u32, u32, dp, dp,
                                    C.POINTER(C.c_int64), ip]
         L.orc_dock.argtypes = [vp, vp, C.POINTER(DockParams), C.c_uint64, u32, dp, dp,
@@ -281,6 +290,22 @@ class Oracle:
         if rc:
             raise ValueError("oracle adadelta failed (%d)" % rc)
         return best, E.value
+
+    def solis_wets(self, L, G, params, geno, max_ev, seed, lig, run, gen, indiv, E_in=float("nan")):
+        """Returns (best genotype, its energy, evaluations used)."""
+        g = np.zeros(STRIDE)
+        g[:len(geno)] = np.asarray(geno, dtype=np.float64)[:STRIDE]
+        best = np.zeros(STRIDE)
+        E = C.c_double()
+        used = C.c_int()
+        rc = self.L.orc_solis_wets(L.h, G.h, C.byref(params), _p(g, C.c_double), E_in, max_ev, seed, lig, run, gen,
+                                   indiv, _p(best, C.c_double), C.byref(E), C.byref(used))
+        if rc:
+            raise ValueError("oracle solis-wets failed (%d)" % rc)
+        return best, E.value, used.value
+
+    def sw_deviate(self, seed, lig, run, gen, indiv, it, k):
+        return float(self.L.orc_sw_deviate(seed, lig, run, gen, indiv, it, k))
 
     def n_ls(self, params):
         return int(self.L.orc_n_ls(C.byref(params)))

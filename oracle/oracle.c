@@ -823,6 +823,110 @@ int orc_adadelta(const orc_ligand *L, orc_grid *g, const orc_dock_params *p, con
   return ORC_OK;
 }
 
+/* Solis-Wets random local search (Solis and Wets 1981; the energy-only
+ * local search of the LGA, Sec. 1.1), reading: a deviate
+ * d_k ~ N(0, (rho s_k)^2) per degree of freedom (s = sw_sigma_t for
+ * translation, sw_sigma_ang for the rotation vector and the torsions); the
+ * candidate x + b + d is tried first and, if it is not better, x - b - d.
+ * On success at x + b + d the bias becomes 0.2 b + 0.4 d, on success at
+ * x - b - d it becomes b - 0.4 d, and when both fail it is halved.  After
+ * sw_max_succ consecutive successes rho doubles, after sw_max_fail
+ * consecutive failures it halves.  The search stops when `max_ev`
+ * evaluations are used or rho drops below sw_rho_lb; only improvements are
+ * accepted, so the final point is the best one.  E_in is the energy of
+ * geno_in (evaluated here, counting one evaluation, if it is NaN).
+ * Random numbers: Philox with key (seed lo, seed hi ^ 0x9E3779B9) and
+ * counter (ligand, run, generation << 16 | individual, iteration << 8 |
+ * block); degree of freedom k uses block k/2 and the Box-Muller pair of its
+ * words 0 and 1, u1 = ((w0 >> 8) + 1) 2^-24, u2 = (w1 >> 8) 2^-24, taking
+ * the cosine branch for even k and the sine branch for odd k. */
+static double orc_sw_normal(uint64_t seed, uint32_t lig, uint32_t run, uint32_t gen, uint32_t indiv, uint32_t it,
+                            int k) {
+  uint32_t ctr[4] = {lig, run, (gen << 16) | indiv, (it << 8) | (uint32_t)(k >> 1)};
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32) ^ 0x9E3779B9u};
+  uint32_t w[4];
+  orc_philox4x32_10(ctr, key, w);
+  double u1 = (double)((w[0] >> 8) + 1) * (1.0 / 16777216.0);
+  double u2 = (double)(w[1] >> 8) * (1.0 / 16777216.0);
+  double r = sqrt(-2.0 * log(u1));
+  return (k & 1) ? r * sin(2 * PI * u2) : r * cos(2 * PI * u2);
+}
+
+double orc_sw_deviate(uint64_t seed, uint32_t lig, uint32_t run, uint32_t gen, uint32_t indiv, uint32_t it, int k) {
+  return orc_sw_normal(seed, lig, run, gen, indiv, it, k);
+}
+
+/* x <- x + sgn (b + d) over the degrees of freedom (t, omega, theta) */
+static void orc_sw_move(const orc_ligand *L, double *x, const double *b, const double *d, double sgn) {
+  double w[3];
+  for (int c = 0; c < 3; c++) x[c] += sgn * (b[c] + d[c]);
+  for (int c = 0; c < 3; c++) w[c] = sgn * (b[3 + c] + d[3 + c]);
+  orc_apply_rotvec(&x[3], w);
+  for (int k = 0; k < L->n_tor; k++) x[7 + k] = orc_wrap(x[7 + k] + sgn * (b[6 + k] + d[6 + k]));
+}
+
+int orc_solis_wets(const orc_ligand *L, orc_grid *g, const orc_dock_params *p, const double *geno_in, double E_in,
+                   int max_ev, uint64_t seed, uint32_t lig, uint32_t run, uint32_t gen, uint32_t indiv,
+                   double *best_geno, double *best_E, int *evals_used) {
+  double x[ORC_STRIDE], xt[ORC_STRIDE];
+  memcpy(x, geno_in, sizeof(x));
+  int nd = 6 + L->n_tor, ev = 0, rc = ORC_OK;
+  double Ex = E_in;
+  if (isnan(Ex) && max_ev > 0) {
+    rc = orc_score(L, g, x, &Ex, NULL, NULL, NULL);
+    ev++;
+  }
+  double b[6 + ORC_MAXTOR] = {0}, d[6 + ORC_MAXTOR];
+  double rho = p->sw_rho;
+  int succ = 0, fail = 0;
+  for (uint32_t it = 0; !rc && ev < max_ev && rho >= p->sw_rho_lb; it++) {
+    for (int k = 0; k < nd; k++)
+      d[k] = rho * (k < 3 ? p->sw_sigma_t : p->sw_sigma_ang) * orc_sw_normal(seed, lig, run, gen, indiv, it, k);
+    double Et;
+    memcpy(xt, x, sizeof(x));
+    orc_sw_move(L, xt, b, d, 1.0);
+    rc |= orc_score(L, g, xt, &Et, NULL, NULL, NULL);
+    ev++;
+    int ok = 0;
+    if (Et < Ex) {
+      memcpy(x, xt, sizeof(x));
+      Ex = Et;
+      for (int k = 0; k < nd; k++) b[k] = 0.2 * b[k] + 0.4 * d[k];
+      ok = 1;
+    } else if (ev < max_ev) {
+      memcpy(xt, x, sizeof(x));
+      orc_sw_move(L, xt, b, d, -1.0);
+      rc |= orc_score(L, g, xt, &Et, NULL, NULL, NULL);
+      ev++;
+      if (Et < Ex) {
+        memcpy(x, xt, sizeof(x));
+        Ex = Et;
+        for (int k = 0; k < nd; k++) b[k] = b[k] - 0.4 * d[k];
+        ok = 1;
+      }
+    }
+    if (ok) {
+      succ++;
+      fail = 0;
+    } else {
+      for (int k = 0; k < nd; k++) b[k] *= 0.5;
+      fail++;
+      succ = 0;
+    }
+    if (succ >= p->sw_max_succ) {
+      rho *= 2.0;
+      succ = 0;
+    } else if (fail >= p->sw_max_fail) {
+      rho *= 0.5;
+      fail = 0;
+    }
+  }
+  memcpy(best_geno, x, sizeof(x));
+  *best_E = Ex;
+  *evals_used = ev;
+  return rc;
+}
+
 int orc_n_ls(const orc_dock_params *p) {
   int n = (int)floor(p->ls_rate * p->pop + 0.5);
   if (n > p->pop - 1) n = p->pop - 1;
@@ -850,23 +954,49 @@ int orc_dock_run(const orc_ligand *L, orc_grid *g, const orc_dock_params *p, uin
   }
   evals += pop;
   int n_ls = orc_n_ls(p);
-  int64_t per_gen = (pop - 1) + (int64_t)n_ls * p->ls_iters;
+  /* the most a generation can cost: ADADELTA uses exactly ls_iters
+   * evaluations per local search, Solis-Wets at most ls_iters */
+  int64_t per_gen_max = (pop - 1) + (int64_t)n_ls * p->ls_iters;
   int gen = 1;
   int picked[ORC_MAXPOP];
-  while (!rc && gen <= p->max_gens && evals + per_gen <= p->max_evals) {
+  /* autostop (reading): the best energy of the population after every
+   * generation (generation 0 included); a run stops once 10 of them are
+   * recorded and their standard deviation (over the last 10, divided by
+   * 10) is below stop_std */
+  double hist[10];
+  int nh = 0;
+  hist[nh++ % 10] = E0[orc_argmin(E0, pop)];
+  for (;;) {
+    if (rc || gen > p->max_gens || evals + per_gen_max > p->max_evals) break;
+    if (p->autostop && nh >= 10) {
+      double m = 0, v = 0;
+      for (int k = 0; k < 10; k++) m += hist[k];
+      m /= 10;
+      for (int k = 0; k < 10; k++) v += (hist[k] - m) * (hist[k] - m);
+      if (sqrt(v / 10) < p->stop_std) break;
+    }
     orc_ga_offspring(L, p, seed, lig, run, (uint32_t)gen, pop, G0, E0, G1, E1);
     for (int i = 1; i < pop; i++) rc |= orc_score(L, g, &G1[(size_t)i * ORC_STRIDE], &E1[i], NULL, NULL, NULL);
+    evals += pop - 1;
     orc_ls_pick(seed, lig, run, (uint32_t)gen, pop, n_ls, picked);
     for (int s = 0; s < n_ls; s++) {
       int i = picked[s];
       double bg[ORC_STRIDE], bE;
-      rc |= orc_adadelta(L, g, p, &G1[(size_t)i * ORC_STRIDE], p->ls_iters, bg, &bE);
+      if (p->ls_method == 1) {
+        int used = 0;
+        rc |= orc_solis_wets(L, g, p, &G1[(size_t)i * ORC_STRIDE], E1[i], p->ls_iters, seed, lig, run,
+                             (uint32_t)gen, (uint32_t)i, bg, &bE, &used);
+        evals += used;
+      } else {
+        rc |= orc_adadelta(L, g, p, &G1[(size_t)i * ORC_STRIDE], p->ls_iters, bg, &bE);
+        evals += p->ls_iters;
+      }
       memcpy(&G1[(size_t)i * ORC_STRIDE], bg, sizeof(bg));
       E1[i] = bE;
     }
-    evals += per_gen;
     double *t = G0; G0 = G1; G1 = t;
     t = E0; E0 = E1; E1 = t;
+    hist[nh++ % 10] = E0[orc_argmin(E0, pop)];
     gen++;
   }
   int b = orc_argmin(E0, pop);

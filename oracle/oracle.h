@@ -82,6 +82,12 @@ typedef struct {
   double cx_rate, mut_rate, tour_p;
   double rho, eps;                /* ADADELTA */
   double mut_t, mut_theta, mut_rot;
+  int ls_method;                  /* 0 ADADELTA, 1 Solis-Wets */
+  int autostop;                   /* 1: stop a run when its best energy has settled */
+  double sw_rho, sw_rho_lb;       /* Solis-Wets step size: initial, lower bound */
+  int sw_max_succ, sw_max_fail;   /* consecutive successes / failures that expand / contract */
+  double sw_sigma_t, sw_sigma_ang;/* deviate scale per unit step: translation (A), angles (rad) */
+  double stop_std;                /* autostop threshold (kcal/mol) over the last 10 generations */
 } orc_dock_params;
 
 /* error codes (mirrors the meaning, not the code, of the product's) */
