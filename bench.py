@@ -206,6 +206,10 @@ def main():
     ap.add_argument("--campaign-evals", type=int, default=100_000, help="evaluation cap per run in the campaign")
     ap.add_argument("--holdout", type=int, default=2048)
     ap.add_argument("--screen-frac", type=float, default=0.1)
+    ap.add_argument("--max-evals", type=int, default=None,
+                    help="override the workload's evaluation cap per run (short profiled runs)")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="first run a plain device copy of this many MiB three times (reference for HBM counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -221,8 +225,19 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     t0 = time.time()
+    if args.calibrate_copy_mib > 0:
+        n = args.calibrate_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)   # reads and writes n * 4 bytes
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 x {args.calibrate_copy_mib} MiB read + written")
+        del src, dst
     c = workload(args.workload)
     dock = c["dock"]
+    if args.max_evals is not None:
+        dock = dict(dock, max_evals=args.max_evals)
     log(f"workload {args.workload}: {len(c['ligands'])} ligands generated in {time.time() - t0:.1f}s")
     ctx = pkg.create(synth.forcefield(), 0)
     t0 = time.time()
@@ -252,6 +267,13 @@ def main():
     elapsed = time.perf_counter() - t0
     kt = ctx.ad_get_kernel_timing(reset=True)
     ctx.ad_set_kernel_timing(False)
+    schedule = ctx.ad_get_schedule()
+    # the same step replayed as a graph (kernel timing off), for comparison
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.ad_dock_batch(batch, params, seed)
+    graph_ms = (time.perf_counter() - t0) * 1e3
+    schedule_graph = ctx.ad_get_schedule()
 
     n_lig = batch.n
     ligands_s = n_lig * args.steps / elapsed
@@ -304,6 +326,8 @@ def main():
         },
     }
     # score-grad evaluations per second inside the local-search kernel
+    out["schedule"] = {"timed_steps": {"graph": schedule["graph"], "ls_stage_pairs": schedule["stage_pairs"]},
+                       "graph_replay_ms_per_step": round(graph_ms, 2), "graph": schedule_graph["graph"]}
     out["score_grad_evals_per_s"] = round(dock["nrun"] * n_lig * n_ls * dock["ls_iters"] / ls_avg_s, 1)
     batch.free()
     ctx.close()

@@ -195,8 +195,23 @@ typedef struct {
   double cx_rate, mut_rate, tour_p;
   double rho, eps;
   double mut_t, mut_theta, mut_rot;
-  int ls_method;   /* 0 = ADADELTA (others: AD_E_UNSUPPORTED) */
-  int autostop;    /* must be 0 (AD_E_UNSUPPORTED otherwise) */
+  int ls_method;   /* 0 = ADADELTA (gradient), 1 = Solis-Wets (energy only); others AD_E_UNSUPPORTED */
+  int autostop;    /* 1: a run stops once its best energy has settled (below) */
+  /* Solis-Wets (Sec. 1.1; Solis and Wets 1981): per degree of freedom a
+   * deviate d ~ N(0, (rho s)^2), s = sw_sigma_t (A) for translation and
+   * sw_sigma_ang (rad) for the rotation vector and torsions; x + b + d is
+   * tried, then x - b - d; the bias b becomes 0.2 b + 0.4 d, b - 0.4 d or
+   * b / 2 (both failed); rho doubles after sw_max_succ consecutive
+   * successes and halves after sw_max_fail consecutive failures; a search
+   * stops after ls_iters evaluations or when rho < sw_rho_lb.  Each
+   * evaluation counts towards max_evals. */
+  double sw_rho, sw_rho_lb;     /* 1.0, 0.01 */
+  int sw_max_succ, sw_max_fail; /* 4, 4 */
+  double sw_sigma_t, sw_sigma_ang; /* 1.0 A, 0.2 rad */
+  /* autostop (Sec. 1.1): after every generation the run records the best
+   * energy of its population; it stops once ten are recorded and their
+   * standard deviation (over the last ten) is below stop_std (kcal/mol). */
+  double stop_std;              /* 0.15 */
 } ad_dock_params;
 
 typedef struct {
@@ -204,7 +219,7 @@ typedef struct {
   float best_score;                   /* inter + w_tor*T at that pose */
   float best_genotype[AD_GENO_STRIDE];
   int best_run;
-  int generations;                    /* generations per run */
+  int generations;                    /* generations of the best run */
   int64_t evals;                      /* evaluations over all runs */
 } ad_dock_result;
 
@@ -232,6 +247,15 @@ int ad_dock_select(ad_ctx *ctx, const ad_batch *b, int n, const int *lig_idx, co
  * pose and energy its energy (Lamarckian write-back).  Uses p->rho, p->eps. */
 int ad_local_search(ad_ctx *ctx, const ad_batch *b, int n, const int *lig_idx, float *genotypes, float *energy,
                     const ad_dock_params *p, int iters, int ptrs_on_device);
+
+/* ad_solis_wets: Solis-Wets local search (parameters sw_* of p) on n given
+ * poses (host arrays: lig_idx [n], genotypes [n][40] in/out, energy [n]
+ * out, evals_used [n] out, optional).  The start pose is evaluated first
+ * (one evaluation), then at most max_evals - 1 more; on return genotypes
+ * hold the best pose found.  Random streams: ligand id = lig_idx[i],
+ * run 0, generation 0, individual i (n <= 65536). */
+int ad_solis_wets(ad_ctx *ctx, const ad_batch *b, int n, const int *lig_idx, float *genotypes, float *energy,
+                  int *evals_used, const ad_dock_params *p, int max_evals, uint64_t seed);
 
 /* Diagnostics: the initial population genotypes of generation 0 for
  * (ligand, run), [pop][40] host, exactly as ad_dock_batch draws them. */

@@ -26,7 +26,7 @@ MAX_TYPES, STRIDE = 16, 40
 
 EXPORTS = ["ad_create", "ad_destroy", "ad_last_error", "ad_set_stream", "ad_synchronize", "ad_load_grids",
            "ad_build_grids", "ad_ligand_check", "ad_load_ligands", "ad_free_batch", "ad_batch_info",
-           "ad_score_poses", "ad_dock_batch", "ad_dock_select", "ad_local_search", "ad_initial_population",
+           "ad_score_poses", "ad_dock_batch", "ad_dock_select", "ad_local_search", "ad_solis_wets", "ad_initial_population",
            "ad_set_kernel_timing", "ad_get_kernel_timing", "ad_set_schedule", "ad_get_schedule",
            "ad_prescreen_n_params", "ad_prescreen_create",
            "ad_prescreen_destroy", "ad_prescreen_set_params", "ad_prescreen_get_params", "ad_prescreen_set_scale",
@@ -79,7 +79,9 @@ class DockParams(C.Structure):
                 ("ls_rate", C.c_double), ("ls_iters", C.c_int), ("cx_rate", C.c_double),
                 ("mut_rate", C.c_double), ("tour_p", C.c_double), ("rho", C.c_double), ("eps", C.c_double),
                 ("mut_t", C.c_double), ("mut_theta", C.c_double), ("mut_rot", C.c_double),
-                ("ls_method", C.c_int), ("autostop", C.c_int)]
+                ("ls_method", C.c_int), ("autostop", C.c_int), ("sw_rho", C.c_double), ("sw_rho_lb", C.c_double),
+                ("sw_max_succ", C.c_int), ("sw_max_fail", C.c_int), ("sw_sigma_t", C.c_double),
+                ("sw_sigma_ang", C.c_double), ("stop_std", C.c_double)]
 
 
 class KernelTimes(C.Structure):
@@ -106,7 +108,8 @@ class DockResult(C.Structure):
 
 DEFAULT_DOCK = dict(nrun=4, pop=50, max_gens=50, max_evals=2**62, ls_rate=0.06, ls_iters=300, cx_rate=0.8,
                     mut_rate=0.02, tour_p=0.6, rho=0.8, eps=1e-2, mut_t=2.0, mut_theta=np.pi / 2,
-                    mut_rot=np.pi / 2, ls_method=0, autostop=0)
+                    mut_rot=np.pi / 2, ls_method=0, autostop=0, sw_rho=1.0, sw_rho_lb=0.01, sw_max_succ=4,
+                    sw_max_fail=4, sw_sigma_t=1.0, sw_sigma_ang=0.2, stop_std=0.15)
 
 _lib = None
 
@@ -146,6 +149,7 @@ def lib():
     L.ad_dock_select.argtypes = [vp, vp, C.c_int, vp, C.POINTER(DockParams), C.c_uint64, C.POINTER(DockResult), fp,
                                  fp]
     L.ad_local_search.argtypes = [vp, vp, C.c_int, vp, vp, vp, C.POINTER(DockParams), C.c_int, C.c_int]
+    L.ad_solis_wets.argtypes = [vp, vp, C.c_int, vp, vp, vp, vp, C.POINTER(DockParams), C.c_int, C.c_uint64]
     L.ad_initial_population.argtypes = [vp, vp, C.c_int, C.c_uint32, C.c_int, C.c_int, C.c_uint64, fp]
     L.ad_set_schedule.argtypes = [vp, C.c_int, C.c_int, C.c_int]
     L.ad_get_schedule.argtypes = [vp, ip, ip]
@@ -385,6 +389,17 @@ class Context:
         self._check(lib().ad_local_search(self.h, batch.h, n, _ptr(idx), _ptr(g), _ptr(E), C.byref(params),
                                           iters, 0))
         return g, E
+
+    def ad_solis_wets(self, batch, lig_idx, genotypes, params: DockParams, max_evals: int, seed: int):
+        """Host arrays: returns (best genotypes, energies, evaluations used)."""
+        g = _np(genotypes, np.float32).copy()
+        n = g.shape[0]
+        idx = _np(lig_idx, np.int32)
+        E = np.empty(n, np.float32)
+        used = np.empty(n, np.int32)
+        self._check(lib().ad_solis_wets(self.h, batch.h, n, _ptr(idx), _ptr(g), _ptr(E), _ptr(used), C.byref(params),
+                                        max_evals, seed))
+        return g, E, used
 
     def ad_dock_batch(self, batch, params: DockParams, seed: int, lig_ids=None, per_run=False):
         n = batch.n

@@ -530,6 +530,54 @@ extern "C" int ad_local_search(ad_ctx *c, const ad_batch *b, int n, const int *l
   return AD_OK;
 }
 
+extern "C" int ad_solis_wets(ad_ctx *c, const ad_batch *b, int n, const int *lig_idx, float *genotypes,
+                             float *energy, int *evals_used, const ad_dock_params *p, int max_evals, uint64_t seed) {
+  if (!c) return AD_E_INVALID;
+  int rc = check_batch(c, b);
+  if (rc) return rc;
+  if (n < 0 || max_evals < 0 || !p) return c->fail(AD_E_INVALID, "bad local-search arguments");
+  if (!(p->sw_rho > 0.0) || !(p->sw_rho_lb > 0.0) || p->sw_max_succ < 1 || p->sw_max_fail < 1 ||
+      !(p->sw_sigma_t >= 0.0) || !(p->sw_sigma_ang >= 0.0))
+    return c->fail(AD_E_INVALID, "bad Solis-Wets parameters");
+  if (n > 65536) return c->fail(AD_E_INVALID, "at most 65536 poses per call");
+  if (n == 0) return AD_OK;
+  if (!lig_idx || !genotypes || !energy) return c->fail(AD_E_INVALID, "null argument");
+  for (int q = 0; q < n; ++q)
+    if (lig_idx[q] < 0 || lig_idx[q] >= b->n_lig) return c->fail(AD_E_INVALID, "lig_idx out of range");
+  hipSetDevice(c->device);
+  const EvalConst C = c->eval_const(b);
+  DockArgs D;
+  memset(&D, 0, sizeof(D));
+  D.ls_iters = max_evals;
+  D.k0 = (uint32_t)seed;
+  D.k1 = (uint32_t)(seed >> 32);
+  D.sw_rho = (float)p->sw_rho;
+  D.sw_rho_lb = (float)p->sw_rho_lb;
+  D.sw_sig_t = (float)p->sw_sigma_t;
+  D.sw_sig_ang = (float)p->sw_sigma_ang;
+  D.sw_max_succ = p->sw_max_succ;
+  D.sw_max_fail = p->sw_max_fail;
+  const size_t nb_idx = ((size_t)n * 4 + 255) & ~(size_t)255;
+  const size_t nb_geo = ((size_t)n * kStride * 4 + 255) & ~(size_t)255;
+  char *blk = (char *)c->scratch_alloc(3 * nb_idx + nb_geo, 0);
+  if (!blk) return c->fail(AD_E_OOM, "cannot allocate staging");
+  int *d_idx = (int *)blk;
+  float *d_geo = (float *)(blk + nb_idx);
+  float *d_e = (float *)(blk + nb_idx + nb_geo);
+  int *d_used = (int *)(blk + 2 * nb_idx + nb_geo);
+  HIP_TRY(c, hipMemcpyAsync(d_idx, lig_idx, (size_t)n * 4, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(d_geo, genotypes, (size_t)n * kStride * 4, hipMemcpyHostToDevice, c->stream));
+  const int t0 = c->timing_begin(2);
+  HIP_TRY(c, launch_solis_wets(C, b->cap, D, n, d_idx, d_geo, d_e, d_used, c->stream));
+  c->timing_end(2, t0);
+  HIP_TRY(c, hipMemcpyAsync(genotypes, d_geo, (size_t)n * kStride * 4, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(energy, d_e, (size_t)n * 4, hipMemcpyDeviceToHost, c->stream));
+  if (evals_used) HIP_TRY(c, hipMemcpyAsync(evals_used, d_used, (size_t)n * 4, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->timing_collect();
+  return AD_OK;
+}
+
 // ---------------------------------------------------------------------------
 // map-builder argument block (force field in double)
 // ---------------------------------------------------------------------------

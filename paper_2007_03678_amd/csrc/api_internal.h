@@ -43,6 +43,19 @@ struct DockArgs {
   int n_runs, nrun, pop, n_ls, ls_iters;
   int n_launch;      // runs covered by a launch: run_order[0..n_launch)
   int stage_pairs;   // local search: pair records staged in LDS per ligand (0: none)
+  // Solis-Wets local search
+  int ls_method;     // 0 ADADELTA, 1 Solis-Wets
+  float sw_rho, sw_rho_lb, sw_sig_t, sw_sig_ang;
+  int sw_max_succ, sw_max_fail;
+  // per-run stopping (variable-cost local search or autostop); null active:
+  // every run takes every generation
+  unsigned int *active;    // [n_runs] 1 while the run continues
+  int *last_gen;           // [n_runs] last completed generation
+  float *hist;             // [n_runs][10] best energy after each generation (ring)
+  int *n_active;           // [G + 1] runs still active after each generation
+  int autostop, max_gens;
+  double stop_std;
+  long long max_evals, max_gen_cost;
   uint32_t k0, k1;
   double cx_rate, mut_rate, tour_p, rho, eps, mut_t, mut_theta, mut_rot;
 };
@@ -52,6 +65,9 @@ hipError_t launch_ga_generation(const EvalConst &C, int cap, const DockArgs &D, 
 hipError_t launch_ls_generation(const EvalConst &C, int cap, const DockArgs &D, int gen, hipStream_t s);
 size_t ls_dynamic_lds(const EvalConst &C, const DockArgs &D);
 hipError_t launch_dock_finalize(const DockArgs &D, int buf, float *best_E, float *best_G, hipStream_t s);
+hipError_t launch_run_status(const DockArgs &D, int gen, hipStream_t s);
+hipError_t launch_solis_wets(const EvalConst &C, int cap, const DockArgs &D, int n, const int *lig_idx, float *geno,
+                             float *E, int *used, hipStream_t s);
 hipError_t launch_init_genotypes(const GridArgs &G, int n_tor, uint32_t k0, uint32_t k1, uint32_t lig_id, int run,
                                  int pop, float *out, hipStream_t s);
 hipError_t launch_score(const EvalConst &C, int cap, int n, const int *lig_idx, const float *geno, float *E, float *G,

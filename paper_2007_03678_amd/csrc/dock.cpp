@@ -28,8 +28,16 @@ namespace {
 
 int check_params(ad_ctx *c, const ad_dock_params *p) {
   if (!p) return c->fail(AD_E_INVALID, "null params");
-  if (p->ls_method != 0) return c->fail(AD_E_UNSUPPORTED, "only ADADELTA local search (ls_method 0) is built");
-  if (p->autostop != 0) return c->fail(AD_E_UNSUPPORTED, "autostop is not built");
+  if (p->ls_method != 0 && p->ls_method != 1)
+    return c->fail(AD_E_UNSUPPORTED, "ls_method must be 0 (ADADELTA) or 1 (Solis-Wets)");
+  if (p->autostop != 0 && p->autostop != 1) return c->fail(AD_E_INVALID, "autostop must be 0 or 1");
+  if (p->ls_method == 1 &&
+      (!(p->sw_rho > 0.0) || !(p->sw_rho_lb > 0.0) || !std::isfinite(p->sw_rho) || p->sw_max_succ < 1 ||
+       p->sw_max_fail < 1 || !(p->sw_sigma_t >= 0.0) || !(p->sw_sigma_ang >= 0.0) || !std::isfinite(p->sw_sigma_t) ||
+       !std::isfinite(p->sw_sigma_ang)))
+    return c->fail(AD_E_INVALID, "bad Solis-Wets parameters");
+  if (p->autostop && (!(p->stop_std >= 0.0) || !std::isfinite(p->stop_std)))
+    return c->fail(AD_E_INVALID, "bad autostop threshold");
   if (p->nrun < 1 || p->pop < 2 || p->pop > AD_MAX_POP || p->max_gens < 0 || p->max_evals < 0 || p->ls_iters < 0)
     return c->fail(AD_E_INVALID, "need nrun >= 1, 2 <= pop <= 4096, max_gens, max_evals, ls_iters >= 0");
   const double r[] = {p->ls_rate, p->cx_rate, p->mut_rate, p->tour_p};
@@ -204,7 +212,17 @@ int dock_impl(ad_ctx *c, const ad_batch *b, int n_lig, const int *sel, const ad_
     return c->fail(AD_E_INVALID, "n_lig * nrun * pop too large for one batch");
   const int n_runs = n_lig * p->nrun;
   const int n_ls = n_local_search(p);
-  const int G = generations(p, n_ls);
+  // Fixed-cost schedule (ADADELTA without autostop): every run takes exactly
+  // G generations.  Otherwise runs stop on their own (k_run_status) and G
+  // is the most that the cheapest generations (no local-search evaluation)
+  // could reach.
+  const bool per_run = p->ls_method == 1 || p->autostop;
+  int G = generations(p, n_ls);
+  if (per_run) {
+    ad_dock_params q = *p;
+    q.ls_iters = 0;
+    G = generations(&q, n_ls);
+  }
 
   // device state, carved out of one grow-only buffer
   const size_t sz_geno = align256((size_t)2 * n_runs * p->pop * kStride * sizeof(float));
@@ -219,8 +237,12 @@ int dock_impl(ad_ctx *c, const ad_batch *b, int n_lig, const int *sel, const ad_
   const size_t sz_lT = align256((size_t)n_lig * 3 * sizeof(float));
   const size_t sz_li = align256((size_t)n_lig * sizeof(int));
   const size_t sz_map = sel ? align256((size_t)n_lig * sizeof(int)) : 0;
-  const size_t total =
-      sz_geno + sz_E + sz_ev + sz_ord + sz_id + sz_bE + sz_bG + sz_lG + sz_lE + sz_lT + sz_li + sz_map;
+  const size_t sz_act = per_run ? align256((size_t)n_runs * sizeof(unsigned int)) : 0;
+  const size_t sz_lgen = per_run ? align256((size_t)n_runs * sizeof(int)) : 0;
+  const size_t sz_hist = per_run ? align256((size_t)n_runs * 10 * sizeof(float)) : 0;
+  const size_t sz_nact = per_run ? align256((size_t)(G + 1) * sizeof(int)) : 0;
+  const size_t total = sz_geno + sz_E + sz_ev + sz_ord + sz_id + sz_bE + sz_bG + sz_lG + sz_lE + sz_lT + sz_li +
+                       sz_map + sz_act + sz_lgen + sz_hist + sz_nact;
   hipSetDevice(c->device);
   if (c->dock_bytes < total) {
     hipStreamSynchronize(c->stream);
@@ -248,9 +270,25 @@ int dock_impl(ad_ctx *c, const ad_batch *b, int n_lig, const int *sel, const ad_
   float *d_lT = (float *)carve(sz_lT);
   int *d_li = (int *)carve(sz_li);
   int *d_map = sel ? (int *)carve(sz_map) : nullptr;
+  D.active = per_run ? (unsigned int *)carve(sz_act) : nullptr;
+  D.last_gen = per_run ? (int *)carve(sz_lgen) : nullptr;
+  D.hist = per_run ? (float *)carve(sz_hist) : nullptr;
+  D.n_active = per_run ? (int *)carve(sz_nact) : nullptr;
   D.run_order = d_order;
   D.lig_id = d_id;
   D.lig_map = d_map;
+  D.ls_method = p->ls_method;
+  D.sw_rho = (float)p->sw_rho;
+  D.sw_rho_lb = (float)p->sw_rho_lb;
+  D.sw_sig_t = (float)p->sw_sigma_t;
+  D.sw_sig_ang = (float)p->sw_sigma_ang;
+  D.sw_max_succ = p->sw_max_succ;
+  D.sw_max_fail = p->sw_max_fail;
+  D.autostop = p->autostop;
+  D.max_gens = p->max_gens;
+  D.stop_std = p->stop_std;
+  D.max_evals = (long long)p->max_evals;
+  D.max_gen_cost = (long long)(p->pop - 1) + (long long)n_ls * p->ls_iters;
   D.n_runs = n_runs;
   D.nrun = p->nrun;
   D.pop = p->pop;
@@ -293,6 +331,11 @@ int dock_impl(ad_ctx *c, const ad_batch *b, int n_lig, const int *sel, const ad_
   if (sel) HIP_TRY(c, hipMemcpyAsync(d_map, sel, n_lig * sizeof(int), hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipMemcpyAsync(d_id, ids.data(), n_lig * sizeof(uint32_t), hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipMemsetAsync(D.evals, 0, (size_t)n_runs * sizeof(unsigned long long), c->stream));
+  if (per_run) {
+    HIP_TRY(c, hipMemsetAsync(D.active, 1, (size_t)n_runs * sizeof(unsigned int), c->stream));
+    HIP_TRY(c, hipMemsetAsync(D.last_gen, 0, (size_t)n_runs * sizeof(int), c->stream));
+    HIP_TRY(c, hipMemsetAsync(D.n_active, 0, (size_t)(G + 1) * sizeof(int), c->stream));
+  }
 
   const EvalConst C = c->eval_const(b);
   DockArgs Db[2];
@@ -317,6 +360,10 @@ int dock_impl(ad_ctx *c, const ad_batch *b, int n_lig, const int *sel, const ad_
     c->last_stage[bk] = -1;
     if (!Db[bk].n_launch || !do_ls) continue;
     int st = 0;
+    if (p->ls_method == 1) {   // pair staging applies to the gradient local search only
+      c->last_stage[bk] = 0;
+      continue;
+    }
     rc = choose_stage(c, b, sel, n_lig, C, Db[bk], bk ? 128 : 64, max_pairs[bk], &st);
     if (rc) return rc;
     Db[bk].stage_pairs = st;
@@ -342,9 +389,34 @@ int dock_impl(ad_ctx *c, const ad_batch *b, int n_lig, const int *sel, const ad_
     hipError_t e = hipEventRecord(c->ev_join, c->aux_stream);
     return e != hipSuccess ? e : hipStreamWaitEvent(c->stream, c->ev_join, 0);
   };
-  const bool graph = c->use_graph && !c->timing && G > 0;
+  const bool graph = c->use_graph && !c->timing && G > 0 && !per_run;
   c->last_graph = graph ? 1 : 0;
-  if (!graph) {
+  if (per_run) {
+    // generations until every run has stopped: the status kernel decides
+    // per run after each generation; the host looks every 16 generations
+    HIP_TRY(c, launch_run_status(D, 0, c->stream));
+    for (int gen = 1; gen <= G; ++gen) {
+      const int t1 = c->timing_begin(1);
+      HIP_TRY(c, fork());
+      for (int bk = 0; bk < 2; ++bk) HIP_TRY(c, launch_ga_generation(C, bk ? 128 : 64, Db[bk], gen, bs[bk]));
+      HIP_TRY(c, join());
+      c->timing_end(1, t1);
+      if (do_ls) {
+        const int t2 = c->timing_begin(2);
+        HIP_TRY(c, fork());
+        for (int bk = 0; bk < 2; ++bk) HIP_TRY(c, launch_ls_generation(C, bk ? 128 : 64, Db[bk], gen, bs[bk]));
+        HIP_TRY(c, join());
+        c->timing_end(2, t2);
+      }
+      HIP_TRY(c, launch_run_status(D, gen, c->stream));
+      if (gen % 16 == 0 || gen == G) {
+        int n_act = 0;
+        HIP_TRY(c, hipMemcpyAsync(&n_act, D.n_active + gen, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        if (n_act == 0) break;
+      }
+    }
+  } else if (!graph) {
     for (int gen = 1; gen <= G; ++gen) {
       const int t1 = c->timing_begin(1);
       HIP_TRY(c, fork());
@@ -386,6 +458,9 @@ int dock_impl(ad_ctx *c, const ad_batch *b, int n_lig, const int *sel, const ad_
 
   std::vector<float> bE(n_runs), bG((size_t)n_runs * kStride);
   std::vector<unsigned long long> ev(n_runs);
+  std::vector<int> run_gens(n_runs, G);
+  if (per_run)
+    HIP_TRY(c, hipMemcpyAsync(run_gens.data(), D.last_gen, n_runs * sizeof(int), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipMemcpyAsync(bE.data(), d_bE, n_runs * sizeof(float), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipMemcpyAsync(bG.data(), d_bG, (size_t)n_runs * kStride * sizeof(float), hipMemcpyDeviceToHost,
                             c->stream));
@@ -422,7 +497,7 @@ int dock_impl(ad_ctx *c, const ad_batch *b, int n_lig, const int *sel, const ad_
     r.best_score = lT[(size_t)l * 3 + 2];
     memcpy(r.best_genotype, &lG[(size_t)l * kStride], kStride * sizeof(float));
     r.best_run = best_run[l];
-    r.generations = G;
+    r.generations = run_gens[R];
     int64_t e = 0;
     for (int q = 0; q < p->nrun; ++q) e += (int64_t)ev[l * p->nrun + q];
     r.evals = e;

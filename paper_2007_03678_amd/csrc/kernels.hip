@@ -63,34 +63,44 @@ __device__ __forceinline__ float fast_rsq(float x) { return __builtin_amdgcn_rsq
 // 33 + 33 + 53 significant bits, so k*C1 and k*C2 are exact for |k| < 2^20)
 // to r in [-pi/4, pi/4], then the Taylor series of sin (through r^17) and cos
 // (through r^16) in Horner form: truncation below 1e-17 on that interval.
-// Arguments beyond 1e5 rad take the library routine.
-__device__ __forceinline__ void sincos_f64(double x, double *sn, double *cs) {
+// Arguments beyond 1e5 rad take the library routine.  The constants are read
+// from a table in LDS (`kSinCosTable`, copied by every evaluating kernel):
+// held in registers they would stay live across a local search's whole
+// iteration loop and cost occupancy.
+enum { kScTwoOverPi = 0, kScC1 = 1, kScC2 = 2, kScC3 = 3, kScSin = 4, kScCos = 12, kScN = 20 };
+__device__ const double kSinCosTable[kScN] = {
+    0.6366197723675814,      // 2/pi
+    1.5707963267341256,      // pi/2, first 33 bits
+    6.077100506303966e-11,   // next 33 bits
+    2.0222662487959506e-21,  // remainder
+    // sin: 1/17!, -1/15!, 1/13!, -1/11!, 1/9!, -1/7!, 1/5!, -1/3!
+    2.8114572543455206e-15, -7.647163731819816e-13, 1.6059043836821613e-10, -2.505210838544172e-08,
+    2.7557319223985893e-06, -0.0001984126984126984, 0.008333333333333333, -0.16666666666666666,
+    // cos: 1/16!, -1/14!, 1/12!, -1/10!, 1/8!, -1/6!, 1/4!, -1/2!
+    4.779477332387385e-14, -1.1470745597729725e-11, 2.08767569878681e-09, -2.755731922398589e-07,
+    2.48015873015873e-05, -0.001388888888888889, 0.041666666666666664, -0.5};
+
+// Arguments outside [-1e5, 1e5] (and NaN): the library routine, kept out of
+// line so that its own constants are not hoisted into callers' loops.
+__device__ __attribute__((noinline)) void sincos_f64_far(double x, double *sn, double *cs) { sincos(x, sn, cs); }
+
+__device__ __forceinline__ void sincos_f64(double x, double *sn, double *cs, const double *T) {
   if (!(fabs(x) <= 1.0e5)) {
-    sincos(x, sn, cs);
+    sincos_f64_far(x, sn, cs);
     return;
   }
-  const double k = rint(x * 0.6366197723675814);
-  double r = fma(-k, 1.5707963267341256, x);
-  r = fma(-k, 6.077100506303966e-11, r);
-  r = fma(-k, 2.0222662487959506e-21, r);
+  const double k = rint(x * T[kScTwoOverPi]);
+  double r = fma(-k, T[kScC1], x);
+  r = fma(-k, T[kScC2], r);
+  r = fma(-k, T[kScC3], r);
   const double z = r * r;
-  double ps = 2.8114572543455206e-15;            // 1/17!
-  ps = fma(ps, z, -7.647163731819816e-13);       // -1/15!
-  ps = fma(ps, z, 1.6059043836821613e-10);       // 1/13!
-  ps = fma(ps, z, -2.505210838544172e-08);       // -1/11!
-  ps = fma(ps, z, 2.7557319223985893e-06);       // 1/9!
-  ps = fma(ps, z, -0.0001984126984126984);       // -1/7!
-  ps = fma(ps, z, 0.008333333333333333);         // 1/5!
-  ps = fma(ps, z, -0.16666666666666666);         // -1/3!
+  double ps = T[kScSin];
+#pragma unroll
+  for (int i = 1; i < 8; ++i) ps = fma(ps, z, T[kScSin + i]);
   const double sr = fma(ps * z, r, r);
-  double pc = 4.779477332387385e-14;             // 1/16!
-  pc = fma(pc, z, -1.1470745597729725e-11);      // -1/14!
-  pc = fma(pc, z, 2.08767569878681e-09);         // 1/12!
-  pc = fma(pc, z, -2.755731922398589e-07);       // -1/10!
-  pc = fma(pc, z, 2.48015873015873e-05);         // 1/8!
-  pc = fma(pc, z, -0.001388888888888889);        // -1/6!
-  pc = fma(pc, z, 0.041666666666666664);         // 1/4!
-  pc = fma(pc, z, -0.5);                         // -1/2!
+  double pc = T[kScCos];
+#pragma unroll
+  for (int i = 1; i < 8; ++i) pc = fma(pc, z, T[kScCos + i]);
   const double cr = fma(pc, z, 1.0);
   const int q = ((int)k) & 3;
   const double s0 = (q & 1) ? cr : sr;
@@ -189,7 +199,24 @@ struct EvalLds {
   double geno[kStride];        // genotype being evaluated
   double grad[kStride];        // output gradient
   double rot[9];               // global rotation matrix of the pose
+  double sc[kScN];             // sin / cos constants (kSinCosTable)
 };
+
+// A zero the compiler cannot see through, produced anew by every call.  An
+// address or bound derived from it is recomputed inside a local search's
+// iteration loop instead of being hoisted into a register for the whole
+// loop (one instruction against one register of occupancy).
+__device__ __forceinline__ int opaque_zero() {
+  int z;
+  asm volatile("v_mov_b32 %0, 0" : "=v"(z));
+  return z;
+}
+
+// Per-kernel set-up of the evaluation LDS (before the first barrier).
+template <int CAP>
+__device__ __forceinline__ void init_eval_lds(EvalLds<CAP> &S, int lane) {
+  if (lane < kScN) S.sc[lane] = kSinCosTable[lane];
+}
 
 // Ligand being evaluated.  Per-atom and per-torsion records are re-read from
 // L1-resident global memory inside every evaluation instead of being held in
@@ -214,7 +241,7 @@ __device__ __forceinline__ double grid_energy(const GridArgs &G, double k_out, i
   bool clamped[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    double top = (double)(n[d] - 1);
+    double top = (double)(n[d] - 1 + opaque_zero());
     clamped[d] = !(u[d] >= 0.0 && u[d] <= top);    // NaN counts as clamped
     uc[d] = fmin(fmax(u[d], 0.0), top);             // NaN -> 0 (fmax drops NaN)
     int ii = (int)floor(uc[d]);
@@ -321,8 +348,10 @@ __device__ double evaluate(const EvalConst &C, const LaneLig<CAP> &LL, EvalLds<C
                            double *intra_out, PairStage st = PairStage{0, 0}) {
   constexpr int APL = CAP / 64;
   const LigDesc &L = LL.L;
-  // keep the ligand records below from being hoisted out of a caller's loop
+  // keep the ligand records below from being hoisted out of a caller's loop,
+  // and recompute the lane's addresses per evaluation (opaque_zero)
   asm volatile("" ::: "memory");
+  lane += opaque_zero();
   // global rigid transform x = R y + t (y relative to the centre): R from the
   // normalised quaternion, one element per lane, kept in LDS
   const double t0 = S.geno[0], t1 = S.geno[1], t2 = S.geno[2];
@@ -350,7 +379,7 @@ __device__ double evaluate(const EvalConst &C, const LaneLig<CAP> &LL, EvalLds<C
     const double to[3] = {tr.o[0], tr.o[1], tr.o[2]};
     const double tu[3] = {tr.u[0], tr.u[1], tr.u[2]};
     double sn, cs, Rk[9];
-    sincos_f64(S.geno[7 + lane], &sn, &cs);
+    sincos_f64(S.geno[7 + lane], &sn, &cs, S.sc + opaque_zero());
     rot_matrix(tu, cs, sn, Rk);
 #pragma unroll
     for (int e = 0; e < 9; ++e) S.tm[lane][e] = Rk[e];
@@ -497,6 +526,7 @@ __global__ __launch_bounds__(64) void k_score(EvalConst C, int n, const int *__r
                                               const float *__restrict__ geno, float *__restrict__ E_out,
                                               float *__restrict__ G_out, float *__restrict__ T_out) {
   __shared__ EvalLds<CAP> S;
+  init_eval_lds(S, threadIdx.x);
   const int p = blockIdx.x;
   const int lane = threadIdx.x;
   const int li = lig_idx[p];
@@ -543,9 +573,11 @@ __device__ void adadelta_wave(const EvalConst &C, const LaneLig<CAP> &LL, EvalLd
   double best_E = INFINITY;
   double Eg2 = 0.0;
   float Edx2 = 0.0f;
-  const float rho = (float)rho_d, eps = (float)eps_d;
   const bool dof = lane < 6 || (lane >= 7 && lane < 7 + T);
   for (int it = 0; it < iters; ++it) {
+    // step constants recomputed from the (scalar) arguments every iteration
+    const double zd = (double)opaque_zero();
+    const float rho = (float)(rho_d + zd), eps = (float)(eps_d + zd);
     if (lane < kStride) S.geno[lane] = (double)gene;
     __syncthreads();
     const double E = evaluate<CAP, true, STAGE>(C, LL, S, lane, nullptr, nullptr, st);
@@ -554,7 +586,7 @@ __device__ void adadelta_wave(const EvalConst &C, const LaneLig<CAP> &LL, EvalLd
       best_E = E;
       best_gene = gene;
     }
-    Eg2 = rho_d * Eg2 + (1.0 - rho_d) * gd * gd;
+    Eg2 = (rho_d + zd) * Eg2 + (1.0 - (rho_d + zd)) * gd * gd;
     const float rg = fast_rsq((float)(Eg2 + eps_d));
     const float dx = dof ? -__builtin_sqrtf(Edx2 + eps) * rg * (float)gd : 0.0f;
     Edx2 = rho * Edx2 + (1.0f - rho) * dx * dx;
@@ -592,6 +624,7 @@ __global__ __launch_bounds__(64) void k_local_search(EvalConst C, int n, const i
                                                      float *__restrict__ geno, float *__restrict__ E, int iters,
                                                      double rho, double eps) {
   __shared__ EvalLds<CAP> S;
+  init_eval_lds(S, threadIdx.x);
   const int p = blockIdx.x;
   const int lane = threadIdx.x;
   const int li = lig_idx[p];
@@ -647,6 +680,7 @@ __device__ double init_gene(const GridArgs &G, const Rng &rng, int indiv, int la
 template <int CAP>
 __global__ __launch_bounds__(64) void k_init_pop(EvalConst C, DockArgs D) {
   __shared__ EvalLds<CAP> S;
+  init_eval_lds(S, threadIdx.x);
   const int lane = threadIdx.x;
   const int R = D.run_order[blockIdx.x / D.pop];
   const int i = blockIdx.x % D.pop;
@@ -704,8 +738,10 @@ __device__ __forceinline__ int tournament(const float *E, int pop, double tour_p
 template <int CAP>
 __global__ __launch_bounds__(64) void k_ga_generation(EvalConst C, DockArgs D, int gen) {
   __shared__ EvalLds<CAP> S;
+  init_eval_lds(S, threadIdx.x);
   const int lane = threadIdx.x;
   const int R = D.run_order[blockIdx.x / D.pop];
+  if (D.active && !D.active[R]) return;   // the run has stopped
   const int i = blockIdx.x % D.pop;
   const int li = R / D.nrun, run = R % D.nrun;
   const int src = (gen - 1) & 1, dst = gen & 1;
@@ -783,10 +819,12 @@ __global__ __launch_bounds__(64) void k_ga_generation(EvalConst C, DockArgs D, i
 template <int CAP, bool STAGE>
 __global__ __launch_bounds__(64) void k_ls_generation(EvalConst C, DockArgs D, int gen) {
   __shared__ EvalLds<CAP> S;
+  init_eval_lds(S, threadIdx.x);
   extern __shared__ __attribute__((aligned(16))) char dyn_lds[];
   int *perm = reinterpret_cast<int *>(dyn_lds);
   const int lane = threadIdx.x;
   const int R = D.run_order[blockIdx.x / D.n_ls];
+  if (D.active && !D.active[R]) return;
   const int slot = blockIdx.x % D.n_ls;
   const int li = R / D.nrun, run = R % D.nrun;
   const int m = D.pop - 1;
@@ -822,10 +860,227 @@ __global__ __launch_bounds__(64) void k_ls_generation(EvalConst C, DockArgs D, i
   if (lane == 0) atomicAdd(&D.evals[R], (unsigned long long)D.ls_iters);
 }
 
-// Best individual of every run after the last generation.
-__global__ __launch_bounds__(64) void k_finalize(DockArgs D, int buf, float *best_E, float *best_G) {
+// ---------------------------------------------------------------------------
+// Solis-Wets local search: one wavefront per individual, energy-only
+// evaluations.  Degrees of freedom on lanes as in ADADELTA (0-2
+// translation, 3-5 rotation vector, 7.. torsions; DOF index k = lane for
+// lane < 6, lane - 1 above).  Deviates: Philox with key (seed lo, seed hi ^
+// 0x9E3779B9), counter (ligand id, run, gen << 16 | individual, it << 8 |
+// k / 2); Box-Muller from words 0, 1 (cosine branch for even k, sine for
+// odd), evaluated in FP32.  Only improvements are accepted.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float sw_normal(uint32_t k0, uint32_t k1, uint32_t lig, uint32_t run, uint32_t gen,
+                                           uint32_t indiv, uint32_t it, int k) {
+  const uint4 w = philox(make_uint4(lig, run, (gen << 16) | indiv, (it << 8) | (uint32_t)(k >> 1)), k0,
+                         k1 ^ 0x9E3779B9u);
+  const float u1 = (float)((w.x >> 8) + 1) * (1.0f / 16777216.0f);
+  const float u2 = (float)(w.y >> 8) * (1.0f / 16777216.0f);
+  const float r = __builtin_sqrtf(-2.0f * 0.69314718055994531f * __builtin_amdgcn_logf(u1));
+  float sn, cs;
+  __sincosf(6.2831853071795865f * u2, &sn, &cs);
+  return (k & 1) ? r * sn : r * cs;
+}
+
+// gene of this lane after moving by sgn * (b + d) (rotation lanes combine
+// the three rotation-vector components into a quaternion update)
+__device__ __forceinline__ float sw_moved(float gene, float step, float sgn, int lane, int T) {
+  const float st = sgn * step;
+  const float w0 = lane_f32(st, 3), w1 = lane_f32(st, 4), w2 = lane_f32(st, 5);
+  const float qw = lane_f32(gene, 3), qx = lane_f32(gene, 4), qy = lane_f32(gene, 5), qz = lane_f32(gene, 6);
+  const float th = __builtin_sqrtf(w0 * w0 + w1 * w1 + w2 * w2);
+  float sh, ch;
+  __sincosf(0.5f * th, &sh, &ch);
+  const float f = th > 1e-30f ? sh / th : 0.5f;
+  const float rx = f * w0, ry = f * w1, rz = f * w2;
+  const float nw = ch * qw - rx * qx - ry * qy - rz * qz;
+  const float nx = ch * qx + rx * qw + ry * qz - rz * qy;
+  const float ny = ch * qy - rx * qz + ry * qw + rz * qx;
+  const float nz = ch * qz + rx * qy - ry * qx + rz * qw;
+  const float inv = fast_rsq(nw * nw + nx * nx + ny * ny + nz * nz);
+  if (lane < 3) return gene + st;
+  if (lane == 3) return nw * inv;
+  if (lane == 4) return nx * inv;
+  if (lane == 5) return ny * inv;
+  if (lane == 6) return nz * inv;
+  if (lane < 7 + T) {
+    float th2 = gene + st;
+    th2 -= 6.2831853071795865f * floorf((th2 + 3.14159265358979f) * 0.15915494309189535f);
+    return th2;
+  }
+  return gene;
+}
+
+template <int CAP>
+__device__ int sw_wave(const EvalConst &C, const LaneLig<CAP> &LL, EvalLds<CAP> &S, int lane, float *geno_io,
+                       float *E_io, const DockArgs &D, uint32_t lig_id, uint32_t run, uint32_t gen, uint32_t indiv) {
+  const int T = LL.L.n_tor;
+  const bool dof = lane < 6 || (lane >= 7 && lane < 7 + T);
+  const int k = lane < 6 ? lane : lane - 1;
+  const float sig = lane < 3 ? D.sw_sig_t : D.sw_sig_ang;
+  float gene = lane < kStride ? geno_io[lane] : 0.0f;
+  double Ex = (double)*E_io;
+  float b = 0.0f, rho = D.sw_rho;
+  int succ = 0, fail = 0, ev = 0;
+  for (uint32_t it = 0; ev < D.ls_iters && rho >= D.sw_rho_lb; ++it) {
+    const float dv = dof ? rho * sig * sw_normal(D.k0, D.k1, lig_id, run, gen, indiv, it, k) : 0.0f;
+    const float step = b + dv;
+    bool ok = false;
+    float cand = sw_moved(gene, step, 1.0f, lane, T);
+    if (lane < kStride) S.geno[lane] = (double)cand;
+    __syncthreads();
+    double E = evaluate<CAP, false>(C, LL, S, lane, nullptr, nullptr);
+    ++ev;
+    if (E < Ex) {
+      gene = cand;
+      Ex = E;
+      b = 0.2f * b + 0.4f * dv;
+      ok = true;
+    } else if (ev < D.ls_iters) {
+      cand = sw_moved(gene, step, -1.0f, lane, T);
+      __syncthreads();
+      if (lane < kStride) S.geno[lane] = (double)cand;
+      __syncthreads();
+      E = evaluate<CAP, false>(C, LL, S, lane, nullptr, nullptr);
+      ++ev;
+      if (E < Ex) {
+        gene = cand;
+        Ex = E;
+        b = b - 0.4f * dv;
+        ok = true;
+      }
+    }
+    if (ok) {
+      ++succ;
+      fail = 0;
+    } else {
+      b *= 0.5f;
+      ++fail;
+      succ = 0;
+    }
+    if (succ >= D.sw_max_succ) {
+      rho *= 2.0f;
+      succ = 0;
+    } else if (fail >= D.sw_max_fail) {
+      rho *= 0.5f;
+      fail = 0;
+    }
+    __syncthreads();
+  }
+  if (lane < kStride) geno_io[lane] = gene;
+  if (lane == 0) *E_io = (float)Ex;
+  return ev;
+}
+
+// Solis-Wets on the individuals picked for generation `gen` (same picks as
+// the ADADELTA generation kernel).  Dynamic LDS: pop ints.
+template <int CAP>
+__global__ __launch_bounds__(64) void k_sw_generation(EvalConst C, DockArgs D, int gen) {
+  __shared__ EvalLds<CAP> S;
+  init_eval_lds(S, threadIdx.x);
+  extern __shared__ __attribute__((aligned(16))) char dyn_lds[];
+  int *perm = reinterpret_cast<int *>(dyn_lds);
+  const int lane = threadIdx.x;
+  const int R = D.run_order[blockIdx.x / D.n_ls];
+  if (D.active && !D.active[R]) return;
+  const int slot = blockIdx.x % D.n_ls;
+  const int li = R / D.nrun, run = R % D.nrun;
+  const int m = D.pop - 1;
+  for (int j = lane; j < m; j += 64) perm[j] = j + 1;
+  __syncthreads();
+  const Rng rng{D.k0, D.k1, D.lig_id[li], (uint32_t)run, (uint32_t)gen};
+  if (lane == 0) {
+    for (int s2 = 0; s2 <= slot; ++s2) {
+      const int r = s2 + (int)randint(rng.word(0, kStLsPick, s2), (uint32_t)(m - s2));
+      const int t = perm[s2];
+      perm[s2] = perm[r];
+      perm[r] = t;
+    }
+  }
+  __syncthreads();
+  const int indiv = perm[slot];
+  LaneLig<CAP> LL;
+  LL.load(C, D.lig_map ? D.lig_map[li] : li, lane);
+  const size_t off = pop_off(D, gen & 1, R) + indiv;
+  const int used = sw_wave<CAP>(C, LL, S, lane, D.geno + off * kStride, D.energy + off, D, D.lig_id[li],
+                                (uint32_t)run, (uint32_t)gen, (uint32_t)indiv);
+  if (lane == 0) atomicAdd(&D.evals[R], (unsigned long long)used);
+}
+
+// Standalone Solis-Wets on given poses (ad_solis_wets): the start energy is
+// evaluated first (one evaluation), then D.ls_iters - 1 more at most.
+// Random streams: ligand id = batch index, run 0, generation 0, individual =
+// pose index.
+template <int CAP>
+__global__ __launch_bounds__(64) void k_solis_wets(EvalConst C, DockArgs D, int n, const int *__restrict__ lig_idx,
+                                                   float *__restrict__ geno, float *__restrict__ E,
+                                                   int *__restrict__ used) {
+  __shared__ EvalLds<CAP> S;
+  init_eval_lds(S, threadIdx.x);
+  const int p = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int li = lig_idx[p];
+  if (li < 0 || li >= C.batch.n_lig || C.batch.lig[li].n_atoms > CAP) {
+    if (lane == 0) {
+      E[p] = __builtin_nanf("");
+      used[p] = 0;
+    }
+    return;
+  }
+  LaneLig<CAP> LL;
+  LL.load(C, li, lane);
+  float *g = geno + (size_t)p * kStride;
+  if (D.ls_iters <= 0) {
+    if (lane == 0) {
+      E[p] = __builtin_nanf("");
+      used[p] = 0;
+    }
+    return;
+  }
+  if (lane < kStride) S.geno[lane] = (double)g[lane];
+  __syncthreads();
+  const double E0 = evaluate<CAP, false>(C, LL, S, lane, nullptr, nullptr);
+  __syncthreads();
+  if (lane == 0) E[p] = (float)E0;
+  __syncthreads();
+  DockArgs Dp = D;
+  Dp.ls_iters = D.ls_iters - 1;
+  const int u = sw_wave<CAP>(C, LL, S, lane, g, E + p, Dp, (uint32_t)li, 0u, 0u, (uint32_t)p);
+  if (lane == 0) used[p] = u + 1;
+}
+
+// After generation `gen` (0: the initial population): record each active
+// run's best energy, then decide whether it takes generation gen + 1 --
+// not beyond max_gens, not if the most the next generation can cost would
+// pass max_evals, and with autostop not once ten recorded best energies
+// have a standard deviation below stop_std.  One wavefront per run.
+__global__ __launch_bounds__(64) void k_run_status(DockArgs D, int gen) {
   const int lane = threadIdx.x;
   const int R = blockIdx.x;
+  if (!D.active[R]) return;
+  const float *E = D.energy + pop_off(D, gen & 1, R);
+  const int b = wave_argmin(E, D.pop, lane);
+  if (lane != 0) return;
+  float *h = D.hist + (size_t)R * 10;
+  h[gen % 10] = E[b];
+  D.last_gen[R] = gen;
+  bool go = gen + 1 <= D.max_gens && (long long)D.evals[R] + D.max_gen_cost <= D.max_evals;
+  if (go && D.autostop && gen + 1 >= 10) {
+    double m = 0.0, v = 0.0;
+    for (int k = 0; k < 10; ++k) m += (double)h[k];
+    m /= 10.0;
+    for (int k = 0; k < 10; ++k) v += ((double)h[k] - m) * ((double)h[k] - m);
+    if (sqrt(v / 10.0) < D.stop_std) go = false;
+  }
+  if (go) atomicAdd(&D.n_active[gen], 1);
+  else D.active[R] = 0u;
+}
+
+// Best individual of every run after the last generation (with per-run
+// stopping: after the run's own last generation).
+__global__ __launch_bounds__(64) void k_finalize(DockArgs D, int buf_all, float *best_E, float *best_G) {
+  const int lane = threadIdx.x;
+  const int R = blockIdx.x;
+  const int buf = D.last_gen ? (D.last_gen[R] & 1) : buf_all;
   const float *E = D.energy + pop_off(D, buf, R);
   const int b = wave_argmin(E, D.pop, lane);
   if (lane < kStride) best_G[(size_t)R * kStride + lane] = D.geno[(pop_off(D, buf, R) + b) * kStride + lane];
@@ -992,6 +1247,11 @@ hipError_t launch_ls_generation(const EvalConst &C, int cap, const DockArgs &D, 
   dim3 block(64);
   dim3 lgrid((unsigned)D.n_launch * D.n_ls);
   const size_t dyn = ls_dynamic_lds(C, D);
+  if (D.ls_method == 1) {
+    if (cap <= 64) hipLaunchKernelGGL((k_sw_generation<64>), lgrid, block, (size_t)D.pop * sizeof(int), s, C, D, gen);
+    else hipLaunchKernelGGL((k_sw_generation<128>), lgrid, block, (size_t)D.pop * sizeof(int), s, C, D, gen);
+    return hipGetLastError();
+  }
   const bool st = D.stage_pairs > 0;
   if (cap <= 64) {
     if (st) hipLaunchKernelGGL((k_ls_generation<64, true>), lgrid, block, dyn, s, C, D, gen);
@@ -1000,6 +1260,19 @@ hipError_t launch_ls_generation(const EvalConst &C, int cap, const DockArgs &D, 
     if (st) hipLaunchKernelGGL((k_ls_generation<128, true>), lgrid, block, dyn, s, C, D, gen);
     else hipLaunchKernelGGL((k_ls_generation<128, false>), lgrid, block, dyn, s, C, D, gen);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_solis_wets(const EvalConst &C, int cap, const DockArgs &D, int n, const int *lig_idx, float *geno,
+                             float *E, int *used, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (cap <= 64) hipLaunchKernelGGL((k_solis_wets<64>), dim3(n), dim3(64), 0, s, C, D, n, lig_idx, geno, E, used);
+  else hipLaunchKernelGGL((k_solis_wets<128>), dim3(n), dim3(64), 0, s, C, D, n, lig_idx, geno, E, used);
+  return hipGetLastError();
+}
+
+hipError_t launch_run_status(const DockArgs &D, int gen, hipStream_t s) {
+  hipLaunchKernelGGL(k_run_status, dim3(D.n_runs), dim3(64), 0, s, D, gen);
   return hipGetLastError();
 }
 

@@ -62,6 +62,7 @@ struct GemmArgs {
   int b_mode;
   const uint16_t *B;
   int ldb;
+  int m_ones;             // A row m_ones (column access) is all ones: C row m_ones = column sums of B (-1: none)
   const float *bias;
   int relu;
   const uint16_t *mask;   // zero where mask[m*ldm + n] <= 0
@@ -77,6 +78,7 @@ struct GemmArgs {
 constexpr int BM = 64, BN = 64, BK = 32, BKP = BK + 8;
 
 __device__ __forceinline__ uint16_t gemm_a(const GemmArgs &g, int m, int k) {
+  if (m == g.m_ones) return (uint16_t)0x3F80;   // 1.0 in BF16
   switch (g.a_mode) {
     case 0: {
       const int r = g.a_rows ? g.a_rows[m] : m;
@@ -88,6 +90,41 @@ __device__ __forceinline__ uint16_t gemm_a(const GemmArgs &g, int m, int k) {
       return g.A1[(size_t)k * g.lda1 + m];
     default:
       return m < g.split ? g.A1[(size_t)k * g.lda1 + m] : g.A2[(size_t)k * g.lda2 + (m - g.split)];
+  }
+}
+
+// Eight consecutive A elements along the operand's contiguous axis as one
+// 16-byte load, or null when they have to be gathered one by one (ragged
+// edge, the split of a concatenated operand, the ones row, misalignment).
+__device__ __forceinline__ const uint16_t *aligned8(const uint16_t *p) {
+  return ((uintptr_t)p & 15) == 0 ? p : nullptr;
+}
+// row-wise modes: A(m, k..k+7)
+__device__ __forceinline__ const uint16_t *a_row8(const GemmArgs &g, int m, int k, int kz1) {
+  if (m >= g.M || m == g.m_ones || k + 8 > kz1) return nullptr;
+  if (g.a_mode == 0) {
+    if (g.a_rows || (g.lda1 & 7)) return nullptr;
+    return aligned8(g.A1 + (size_t)m * g.lda1 + k);
+  }
+  if (k + 8 <= g.split) return (g.lda1 & 7) ? nullptr : aligned8(g.A1 + (size_t)m * g.lda1 + k);
+  if (k >= g.split) return (g.lda2 & 7) ? nullptr : aligned8(g.A2 + (size_t)m * g.lda2 + (k - g.split));
+  return nullptr;
+}
+// column modes: A(m..m+7, k)
+__device__ __forceinline__ const uint16_t *a_col8(const GemmArgs &g, int m, int k, int kz1) {
+  if (k >= kz1 || m + 8 > g.M || (g.m_ones >= m && g.m_ones < m + 8)) return nullptr;
+  if (g.a_mode == 2) return (g.lda1 & 7) ? nullptr : aligned8(g.A1 + (size_t)k * g.lda1 + m);
+  if (m + 8 <= g.split) return (g.lda1 & 7) ? nullptr : aligned8(g.A1 + (size_t)k * g.lda1 + m);
+  if (m >= g.split) return (g.lda2 & 7) ? nullptr : aligned8(g.A2 + (size_t)k * g.lda2 + (m - g.split));
+  return nullptr;
+}
+
+__device__ __forceinline__ void unpack8(const uint4 v, uint16_t h[8]) {
+  const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    h[2 * j] = (uint16_t)(w[j] & 0xffffu);
+    h[2 * j + 1] = (uint16_t)(w[j] >> 16);
   }
 }
 
@@ -103,19 +140,59 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
 #pragma unroll
   for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
   for (int k0 = kz0; k0 < kz1; k0 += BK) {
-    for (int e = tid; e < BM * BK; e += 256) {
-      const int r = a_rowwise ? e / BK : e % BM;
-      const int kk = a_rowwise ? e % BK : e / BM;
-      const int m = m0 + r, k = k0 + kk;
-      As[r][kk] = (m < g.M && k < kz1) ? gemm_a(g, m, k) : (uint16_t)0;
+    // A tile (64 x 32): each thread moves 8 elements along the contiguous axis
+    if (a_rowwise) {
+      const int r = tid >> 2, k8 = (tid & 3) * 8;
+      const int m = m0 + r, k = k0 + k8;
+      const uint16_t *src = a_row8(g, m, k, kz1);
+      if (src) {
+        *reinterpret_cast<uint4 *>(&As[r][k8]) = *reinterpret_cast<const uint4 *>(src);
+      } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) As[r][k8 + j] = (m < g.M && k + j < kz1) ? gemm_a(g, m, k + j) : (uint16_t)0;
+      }
+    } else {
+      const int kk = tid >> 3, m8 = (tid & 7) * 8;
+      const int m = m0 + m8, k = k0 + kk;
+      const uint16_t *src = a_col8(g, m, k, kz1);
+      if (src) {
+        uint16_t h[8];
+        unpack8(*reinterpret_cast<const uint4 *>(src), h);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) As[m8 + j][kk] = h[j];
+      } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) As[m8 + j][kk] = (m + j < g.M && k < kz1) ? gemm_a(g, m + j, k) : (uint16_t)0;
+      }
     }
-    for (int e = tid; e < BN * BK; e += 256) {
-      const int nn = g.b_mode == 0 ? e % BN : e / BK;
-      const int kk = g.b_mode == 0 ? e / BN : e % BK;
-      const int n = n0 + nn, k = k0 + kk;
-      uint16_t v = 0;
-      if (n < g.N && k < kz1) v = g.b_mode == 0 ? g.B[(size_t)k * g.ldb + n] : g.B[(size_t)n * g.ldb + k];
-      Bs[nn][kk] = v;
+    // B tile (32 x 64), stored n-major
+    if (g.b_mode == 0) {   // B[k * ldb + n]: contiguous along n
+      const int kk = tid >> 3, n8 = (tid & 7) * 8;
+      const int n = n0 + n8, k = k0 + kk;
+      const uint16_t *src =
+          (k < kz1 && n + 8 <= g.N && !(g.ldb & 7)) ? aligned8(g.B + (size_t)k * g.ldb + n) : nullptr;
+      if (src) {
+        uint16_t h[8];
+        unpack8(*reinterpret_cast<const uint4 *>(src), h);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) Bs[n8 + j][kk] = h[j];
+      } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          Bs[n8 + j][kk] = (k < kz1 && n + j < g.N) ? g.B[(size_t)k * g.ldb + n + j] : (uint16_t)0;
+      }
+    } else {               // B[n * ldb + k]: contiguous along k
+      const int nn = tid >> 2, k8 = (tid & 3) * 8;
+      const int n = n0 + nn, k = k0 + k8;
+      const uint16_t *src =
+          (n < g.N && k + 8 <= kz1 && !(g.ldb & 7)) ? aligned8(g.B + (size_t)n * g.ldb + k) : nullptr;
+      if (src) {
+        *reinterpret_cast<uint4 *>(&Bs[nn][k8]) = *reinterpret_cast<const uint4 *>(src);
+      } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          Bs[nn][k8 + j] = (n < g.N && k + j < kz1) ? g.B[(size_t)n * g.ldb + k + j] : (uint16_t)0;
+      }
     }
     __syncthreads();
 #pragma unroll
@@ -295,15 +372,6 @@ __global__ void k_head_bwd(const uint16_t *z2, const uint16_t *U3, const float *
   }
 }
 
-// column sums (bias gradients), rows in order
-__global__ void k_colsum(const uint16_t *X, int R, int Cn, float *out) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= Cn) return;
-  float s = 0.0f;
-  for (int r = 0; r < R; ++r) s += bf2f(X[(size_t)r * Cn + c]);
-  out[c] = s;
-}
-
 __global__ void k_adam(float *w, const float *gr, float *m, float *v, size_t n, float lr, float b1, float b2,
                        float eps, float c1, float c2, uint16_t *wbf) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -385,10 +453,11 @@ struct ad_prescreen {
   uint16_t *wbf = nullptr;
   double mean = 0.0, sd = 1.0;
   int64_t step = 0;
-  // grow-only work buffer
+  // grow-only device buffers: activations, and node layouts + labels + losses
   char *work = nullptr;
   size_t work_bytes = 0;
-  std::vector<float> loss_log;
+  char *plan = nullptr;
+  size_t plan_bytes = 0;
 };
 
 namespace {
@@ -401,44 +470,104 @@ namespace {
 
 size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
 
-// minibatch workspace
+// one minibatch: node layout (device), activations (device workspace)
 struct MB {
   int B = 0, Nn = 0;
-  int *node_atom, *node_g0, *node_graph, *gstart;
+  const int *node_atom, *node_g0, *node_graph, *gstart;
   uint16_t *Xmb, *H[kLayers + 1], *M[kLayers + 1], *g, *z1, *z2, *dz1, *dz2, *dg, *dP, *dP2, *dHM;
-  float *p, *y, *dp, *loss, *part;
+  float *p, *dp, *part;
+  const float *y;   // standardised labels (training)
+  float *loss;      // where the loss goes (training)
   size_t part_floats;
 };
 
 constexpr int kSplitRows = 2048;   // nodes per split-K chunk of a weight gradient
 
-int setup_mb(ad_prescreen *ps, const ad_batch *b, const int *sel, int B, bool train, MB *mb) {
-  ad_ctx *c = ps->ctx;
-  std::vector<int> gstart(B + 1, 0);
-  for (int i = 0; i < B; ++i) gstart[i + 1] = gstart[i] + b->lig_host[sel[i]].n_atoms;
-  const int Nn = gstart[B];
-  std::vector<int> na(Nn), ng0(Nn), ngr(Nn);
-  for (int i = 0; i < B; ++i) {
-    const LigDesc &d = b->lig_host[sel[i]];
-    for (int a = 0; a < d.n_atoms; ++a) {
-      na[gstart[i] + a] = d.atom_off + a;
-      ng0[gstart[i] + a] = gstart[i];
-      ngr[gstart[i] + a] = i;
+// Host node layout of minibatches: nodes of graph i of a minibatch are
+// [gstart[i], gstart[i+1]) in minibatch numbering; node_atom maps a node to
+// its batch atom.  Several minibatches are laid out back to back.
+struct Plan {
+  std::vector<int> na, ng0, ngr, gst;   // per node (3) and per minibatch (B + 1 each)
+  std::vector<int> node_off, nn;        // per minibatch: first node, node count
+  std::vector<float> y;                 // labels, B per minibatch
+  int B = 0, max_nn = 0;
+  void add(const ad_batch *b, const int *sel, int B_, const float *ys) {
+    B = B_;
+    node_off.push_back((int)na.size());
+    int acc = 0;
+    for (int i = 0; i < B_; ++i) {
+      const LigDesc &d = b->lig_host[sel[i]];
+      gst.push_back(acc);
+      for (int a = 0; a < d.n_atoms; ++a) {
+        na.push_back(d.atom_off + a);
+        ng0.push_back(acc);
+        ngr.push_back(i);
+      }
+      acc += d.n_atoms;
     }
+    gst.push_back(acc);
+    nn.push_back(acc);
+    max_nn = std::max(max_nn, acc);
+    if (ys) y.insert(y.end(), ys, ys + B_);
   }
-  // split-K partials: the largest of the node-reduced [256 x 128] and the
-  // graph-reduced [256 x 256] weight gradients
+  int steps() const { return (int)nn.size(); }
+};
+
+// device copy of a plan; returns pointers through `base`
+struct PlanDev {
+  int *na, *ng0, *ngr, *gst;
+  float *y, *loss;
+};
+
+int upload_plan(ad_prescreen *ps, const Plan &P, PlanDev *D) {
+  ad_ctx *c = ps->ctx;
+  const size_t n = P.na.size(), ng = P.gst.size(), ny = P.y.size(), ns = (size_t)P.steps();
+  const size_t sz = 3 * al(n * 4 + 4) + al(ng * 4) + al(ny * 4 + 4) + al(ns * 4);
+  if (ps->plan_bytes < sz) {
+    hipStreamSynchronize(c->stream);
+    if (ps->plan) hipFree(ps->plan);
+    ps->plan = nullptr;
+    ps->plan_bytes = 0;
+    if (hipMalloc(&ps->plan, sz) != hipSuccess) return c->fail(AD_E_OOM, "cannot allocate pre-screen batch layout");
+    ps->plan_bytes = sz;
+  }
+  char *q = ps->plan;
+  auto take = [&](size_t bytes) {
+    char *r = q;
+    q += al(bytes);
+    return r;
+  };
+  D->na = (int *)take(n * 4 + 4);
+  D->ng0 = (int *)take(n * 4 + 4);
+  D->ngr = (int *)take(n * 4 + 4);
+  D->gst = (int *)take(ng * 4);
+  D->y = (float *)take(ny * 4 + 4);
+  D->loss = (float *)take(ns * 4);
+  // pageable host memory: the copies complete before the calls return
+  PS_TRY(c, hipMemcpy(D->na, P.na.data(), n * 4, hipMemcpyHostToDevice));
+  PS_TRY(c, hipMemcpy(D->ng0, P.ng0.data(), n * 4, hipMemcpyHostToDevice));
+  PS_TRY(c, hipMemcpy(D->ngr, P.ngr.data(), n * 4, hipMemcpyHostToDevice));
+  PS_TRY(c, hipMemcpy(D->gst, P.gst.data(), ng * 4, hipMemcpyHostToDevice));
+  if (ny) PS_TRY(c, hipMemcpy(D->y, P.y.data(), ny * 4, hipMemcpyHostToDevice));
+  return AD_OK;
+}
+
+// activation workspace for B graphs and up to Nn nodes (grow-only)
+int alloc_ws(ad_prescreen *ps, int B, int Nn, bool train, MB *mb) {
+  ad_ctx *c = ps->ctx;
+  // split-K partials: the largest of the node-reduced [(256+1) x 128] and
+  // the graph-reduced [(256+1) x 256] weight (+ bias) gradients
   const size_t z_nodes = std::max(1, (Nn + kSplitRows - 1) / kSplitRows);
   const size_t z_graphs = std::max(1, (B + kSplitRows - 1) / kSplitRows);
-  const size_t part_floats = std::max(z_nodes * 2 * kW * kW, z_graphs * kH * kH);
-  size_t sz = 4 * al((size_t)Nn * 4) + al((size_t)(B + 1) * 4) + al((size_t)Nn * kFeat * 2);
+  const size_t part_floats = std::max(z_nodes * (2 * kW + 1) * kW, z_graphs * (kH + 1) * kH);
   const size_t hsz = al((size_t)Nn * kW * 2);
-  sz += (kLayers + 1) * hsz + kLayers * hsz;                         // H, M
-  sz += al((size_t)B * kW * 2) + 2 * al((size_t)B * kH * 2);         // g z1 z2
-  sz += 4 * al((size_t)B * 4) + al(4);                                // p y dp loss
+  size_t sz = al((size_t)Nn * kFeat * 2);
+  sz += (kLayers + 1) * hsz + kLayers * hsz;                        // H, M
+  sz += al((size_t)B * kW * 2) + 2 * al((size_t)B * kH * 2);        // g z1 z2
+  sz += 2 * al((size_t)B * 4);                                       // p dp
   if (train) {
-    sz += 2 * al((size_t)B * kH * 2) + al((size_t)B * kW * 2);       // dz1 dz2 dg
-    sz += 2 * hsz + al((size_t)Nn * 2 * kW * 2);                      // dP dP2 dHM
+    sz += 2 * al((size_t)B * kH * 2) + al((size_t)B * kW * 2);      // dz1 dz2 dg
+    sz += 2 * hsz + al((size_t)Nn * 2 * kW * 2);                     // dP dP2 dHM
     sz += al(part_floats * 4);
   }
   if (ps->work_bytes < sz) {
@@ -455,13 +584,6 @@ int setup_mb(ad_prescreen *ps, const ad_batch *b, const int *sel, int B, bool tr
     q += al(n);
     return r;
   };
-  mb->B = B;
-  mb->Nn = Nn;
-  mb->node_atom = (int *)take((size_t)Nn * 4);
-  mb->node_g0 = (int *)take((size_t)Nn * 4);
-  mb->node_graph = (int *)take((size_t)Nn * 4);
-  take((size_t)Nn * 4);
-  mb->gstart = (int *)take((size_t)(B + 1) * 4);
   mb->Xmb = (uint16_t *)take((size_t)Nn * kFeat * 2);
   for (int l = 0; l <= kLayers; ++l) mb->H[l] = (uint16_t *)take((size_t)Nn * kW * 2);
   mb->M[0] = nullptr;
@@ -470,10 +592,7 @@ int setup_mb(ad_prescreen *ps, const ad_batch *b, const int *sel, int B, bool tr
   mb->z1 = (uint16_t *)take((size_t)B * kH * 2);
   mb->z2 = (uint16_t *)take((size_t)B * kH * 2);
   mb->p = (float *)take((size_t)B * 4);
-  mb->y = (float *)take((size_t)B * 4);
   mb->dp = (float *)take((size_t)B * 4);
-  take((size_t)B * 4);
-  mb->loss = (float *)take(4);
   if (train) {
     mb->dz1 = (uint16_t *)take((size_t)B * kH * 2);
     mb->dz2 = (uint16_t *)take((size_t)B * kH * 2);
@@ -484,13 +603,20 @@ int setup_mb(ad_prescreen *ps, const ad_batch *b, const int *sel, int B, bool tr
     mb->part = (float *)take(part_floats * 4);
     mb->part_floats = part_floats;
   }
-  PS_TRY(c, hipMemcpyAsync(mb->node_atom, na.data(), (size_t)Nn * 4, hipMemcpyHostToDevice, c->stream));
-  PS_TRY(c, hipMemcpyAsync(mb->node_g0, ng0.data(), (size_t)Nn * 4, hipMemcpyHostToDevice, c->stream));
-  PS_TRY(c, hipMemcpyAsync(mb->node_graph, ngr.data(), (size_t)Nn * 4, hipMemcpyHostToDevice, c->stream));
-  PS_TRY(c, hipMemcpyAsync(mb->gstart, gstart.data(), (size_t)(B + 1) * 4, hipMemcpyHostToDevice, c->stream));
-  // the host vectors die here: wait for the copies
-  PS_TRY(c, hipStreamSynchronize(c->stream));
   return AD_OK;
+}
+
+// minibatch s of an uploaded plan
+void bind_step(const Plan &P, const PlanDev &D, int s, MB *mb) {
+  mb->B = P.B;
+  mb->Nn = P.nn[s];
+  const int o = P.node_off[s];
+  mb->node_atom = D.na + o;
+  mb->node_g0 = D.ng0 + o;
+  mb->node_graph = D.ngr + o;
+  mb->gstart = D.gst + (size_t)s * (P.B + 1);
+  mb->y = D.y + (size_t)s * P.B;
+  mb->loss = D.loss + s;
 }
 
 GemmArgs gemm_base(int M, int N, int K) {
@@ -500,6 +626,7 @@ GemmArgs gemm_base(int M, int N, int K) {
   g.N = N;
   g.K = K;
   g.k_chunk = K;
+  g.m_ones = -1;
   return g;
 }
 
@@ -509,10 +636,14 @@ hipError_t gemm(const GemmArgs &g, hipStream_t s, int zsplit = 1) {
   return hipGetLastError();
 }
 
-// weight gradient dW[Kin x Nout] = A^T . D with the reduction over R rows in
-// split-K chunks, summed in chunk order into `out`
+// weight gradient and bias gradient in one GEMM: out[0..Kin) = A^T . D and
+// out[Kin] = 1^T . D (the bias follows its weight matrix in the parameter
+// vector), the reduction over R rows split into 2,048-row chunks summed in
+// chunk order
 hipError_t wgrad(const GemmArgs &gbase, int R, float *part, size_t part_floats, float *out, hipStream_t s) {
   GemmArgs g = gbase;
+  g.m_ones = g.M;
+  g.M += 1;
   const int Z = std::max(1, (R + kSplitRows - 1) / kSplitRows);
   g.k_chunk = kSplitRows;
   g.part = part;
@@ -592,7 +723,7 @@ int backward(ad_prescreen *ps, const ad_batch *b, MB &mb) {
   GraphArgs G{mb.node_atom, mb.node_g0, mb.node_graph, mb.gstart, b->ps_nbr, mb.Nn, mb.B};
   hipLaunchKernelGGL(k_head_bwd, dim3(1), dim3(kH), 0, s, mb.z2, ps->wbf + o.U3, mb.dp, mb.B, mb.dz2, gr + o.U3,
                      gr + o.c3);
-  // U2, c2; dz1
+  // U2 and c2; dz1
   GemmArgs g = gemm_base(kH, kH, mb.B);
   g.a_mode = 2;
   g.A1 = mb.z1;
@@ -600,7 +731,6 @@ int backward(ad_prescreen *ps, const ad_batch *b, MB &mb) {
   g.B = mb.dz2;
   g.ldb = kH;
   PS_TRY(c, wgrad(g, mb.B, mb.part, mb.part_floats, gr + o.U2, s));
-  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(kH), 0, s, mb.dz2, mb.B, kH, gr + o.c2);
   g = gemm_base(mb.B, kH, kH);
   g.A1 = mb.dz2;
   g.lda1 = kH;
@@ -612,7 +742,7 @@ int backward(ad_prescreen *ps, const ad_batch *b, MB &mb) {
   g.C16 = mb.dz1;
   g.ldc16 = kH;
   PS_TRY(c, gemm(g, s));
-  // U1, c1; dg
+  // U1 and c1; dg
   g = gemm_base(kW, kH, mb.B);
   g.a_mode = 2;
   g.A1 = mb.g;
@@ -620,7 +750,6 @@ int backward(ad_prescreen *ps, const ad_batch *b, MB &mb) {
   g.B = mb.dz1;
   g.ldb = kH;
   PS_TRY(c, wgrad(g, mb.B, mb.part, mb.part_floats, gr + o.U1, s));
-  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(kH), 0, s, mb.dz1, mb.B, kH, gr + o.c1);
   g = gemm_base(mb.B, kW, kH);
   g.A1 = mb.dz1;
   g.lda1 = kH;
@@ -630,7 +759,7 @@ int backward(ad_prescreen *ps, const ad_batch *b, MB &mb) {
   g.C16 = mb.dg;
   g.ldc16 = kW;
   PS_TRY(c, gemm(g, s));
-  // pool backward, then the message-passing layers
+  // pool backward, then the message-passing layers (W_l and b_l together)
   uint16_t *dP = mb.dP, *dPn = mb.dP2;
   hipLaunchKernelGGL(k_pool_bwd, dim3(nblk((size_t)mb.Nn * kW)), dim3(256), 0, s, G, mb.dg, mb.H[kLayers], dP);
   for (int l = kLayers; l >= 1; --l) {
@@ -644,7 +773,6 @@ int backward(ad_prescreen *ps, const ad_batch *b, MB &mb) {
     g.B = dP;
     g.ldb = kW;
     PS_TRY(c, wgrad(g, mb.Nn, mb.part, mb.part_floats, gr + o.W[l], s));
-    hipLaunchKernelGGL(k_colsum, dim3(1), dim3(kW), 0, s, dP, mb.Nn, kW, gr + o.b[l]);
     g = gemm_base(mb.Nn, 2 * kW, kW);
     g.A1 = dP;
     g.lda1 = kW;
@@ -665,9 +793,19 @@ int backward(ad_prescreen *ps, const ad_batch *b, MB &mb) {
   g.B = dP;
   g.ldb = kW;
   PS_TRY(c, wgrad(g, mb.Nn, mb.part, mb.part_floats, gr + o.W[0], s));
-  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(kW), 0, s, dP, mb.Nn, kW, gr + o.b[0]);
   PS_TRY(c, hipGetLastError());
   return AD_OK;
+}
+
+// forward, loss into mb.loss and dL/dp, backward (gradient into ps->gr)
+int step_grad(ad_prescreen *ps, const ad_batch *b, MB &mb) {
+  ad_ctx *c = ps->ctx;
+  int rc = forward(ps, b, mb);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_loss, dim3(1), dim3(256), 0, c->stream, mb.p, mb.y, mb.B, (float)ps->cfg.lam,
+                     (float)ps->cfg.tau, mb.loss, mb.dp);
+  PS_TRY(c, hipGetLastError());
+  return backward(ps, b, mb);
 }
 
 int check_ps(ad_prescreen *ps, const ad_batch *b, int n, const int *idx) {
@@ -746,6 +884,7 @@ extern "C" void ad_prescreen_destroy(ad_prescreen *ps) {
   hipFree(ps->v);
   hipFree(ps->wbf);
   hipFree(ps->work);
+  hipFree(ps->plan);
   delete ps;
 }
 
@@ -784,6 +923,13 @@ extern "C" int ad_prescreen_set_scale(ad_prescreen *ps, double mean, double sd) 
   return AD_OK;
 }
 
+extern "C" int ad_prescreen_get_scale(ad_prescreen *ps, double *mean, double *sd) {
+  if (!ps) return AD_E_INVALID;
+  if (mean) *mean = ps->mean;
+  if (sd) *sd = ps->sd;
+  return AD_OK;
+}
+
 extern "C" int ad_prescreen_predict(ad_prescreen *ps, const ad_batch *b, int n, const int *lig_idx, float *scores) {
   int rc = check_ps(ps, b, n, lig_idx);
   if (rc) return rc;
@@ -791,44 +937,38 @@ extern "C" int ad_prescreen_predict(ad_prescreen *ps, const ad_batch *b, int n, 
   if (!scores) return ps->ctx->fail(AD_E_INVALID, "null scores");
   ad_ctx *c = ps->ctx;
   hipSetDevice(c->device);
+  // all chunks of up to 2,048 graphs in one layout upload
   const int chunk = 2048;
+  Plan P;
   std::vector<int> sel(chunk);
+  std::vector<int> chunk_n;
   for (int s0 = 0; s0 < n; s0 += chunk) {
     const int B = std::min(chunk, n - s0);
     for (int i = 0; i < B; ++i) sel[i] = lig_idx ? lig_idx[s0 + i] : s0 + i;
-    MB mb;
-    rc = setup_mb(ps, b, sel.data(), B, false, &mb);
-    if (rc) return rc;
+    P.add(b, sel.data(), B, nullptr);
+    P.gst.resize(P.gst.size() + (size_t)(chunk - B));   // uniform stride of chunk + 1 per step
+    chunk_n.push_back(B);
+  }
+  P.B = chunk;
+  PlanDev D;
+  rc = upload_plan(ps, P, &D);
+  if (rc) return rc;
+  MB mb;
+  rc = alloc_ws(ps, chunk, P.max_nn, false, &mb);
+  if (rc) return rc;
+  float *out = mb.dp;   // unused in prediction: holds the rescaled scores
+  for (int s = 0; s < P.steps(); ++s) {
+    bind_step(P, D, s, &mb);
+    mb.B = chunk_n[s];
     rc = forward(ps, b, mb);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_unscale, dim3(nblk(B)), dim3(256), 0, c->stream, mb.p, B, (float)ps->mean, (float)ps->sd,
-                       mb.y);
-    PS_TRY(c, hipMemcpyAsync(scores + s0, mb.y, (size_t)B * 4, hipMemcpyDeviceToHost, c->stream));
+    hipLaunchKernelGGL(k_unscale, dim3(nblk(mb.B)), dim3(256), 0, c->stream, mb.p, mb.B, (float)ps->mean,
+                       (float)ps->sd, out);
+    PS_TRY(c, hipMemcpyAsync(scores + (size_t)s * chunk, out, (size_t)mb.B * 4, hipMemcpyDeviceToHost, c->stream));
     PS_TRY(c, hipStreamSynchronize(c->stream));
   }
   return AD_OK;
 }
-
-namespace {
-
-// forward + loss + backward on one minibatch given on the host
-int step_grad(ad_prescreen *ps, const ad_batch *b, const int *sel, int B, const float *labels_std_host, MB *mbo) {
-  ad_ctx *c = ps->ctx;
-  MB mb;
-  int rc = setup_mb(ps, b, sel, B, true, &mb);
-  if (rc) return rc;
-  PS_TRY(c, hipMemcpyAsync(mb.y, labels_std_host, (size_t)B * 4, hipMemcpyHostToDevice, c->stream));
-  rc = forward(ps, b, mb);
-  if (rc) return rc;
-  hipLaunchKernelGGL(k_loss, dim3(1), dim3(256), 0, c->stream, mb.p, mb.y, B, (float)ps->cfg.lam,
-                     (float)ps->cfg.tau, mb.loss, mb.dp);
-  rc = backward(ps, b, mb);
-  if (rc) return rc;
-  *mbo = mb;
-  return AD_OK;
-}
-
-}  // namespace
 
 extern "C" int ad_prescreen_grad(ad_prescreen *ps, const ad_batch *b, int n, const int *lig_idx, const float *labels,
                                  float *loss, float *grad, float *pred_std) {
@@ -843,8 +983,16 @@ extern "C" int ad_prescreen_grad(ad_prescreen *ps, const ad_batch *b, int n, con
     sel[i] = lig_idx ? lig_idx[i] : i;
     ys[i] = (float)((std::min((double)labels[i], ps->cfg.label_max) - ps->mean) / ps->sd);
   }
+  Plan P;
+  P.add(b, sel.data(), n, ys.data());
+  PlanDev D;
+  rc = upload_plan(ps, P, &D);
+  if (rc) return rc;
   MB mb;
-  rc = step_grad(ps, b, sel.data(), n, ys.data(), &mb);
+  rc = alloc_ws(ps, n, P.max_nn, true, &mb);
+  if (rc) return rc;
+  bind_step(P, D, 0, &mb);
+  rc = step_grad(ps, b, mb);
   if (rc) return rc;
   if (loss) PS_TRY(c, hipMemcpyAsync(loss, mb.loss, 4, hipMemcpyDeviceToHost, c->stream));
   if (grad) PS_TRY(c, hipMemcpyAsync(grad, ps->gr, ps->o.total * 4, hipMemcpyDeviceToHost, c->stream));
@@ -878,41 +1026,49 @@ extern "C" int ad_prescreen_train(ad_prescreen *ps, const ad_batch *b, int n, co
   std::vector<int> sel(Bsz);
   std::vector<float> ys(Bsz);
   std::mt19937_64 rng(seed);
-  const size_t P = ps->o.total;
+  const size_t Pn = ps->o.total;
   for (int ep = 0; ep < epochs; ++ep) {
+    // the epoch's minibatches (full ones only) laid out and uploaded at once;
+    // the steps then run back to back on the stream, losses stay on the device
     std::shuffle(order.begin(), order.end(), rng);
-    double lsum = 0;
-    int nb = 0;
+    Plan P;
     for (int s0 = 0; s0 + Bsz <= n; s0 += Bsz) {
       for (int i = 0; i < Bsz; ++i) {
         const int k = order[s0 + i];
         sel[i] = lig_idx ? lig_idx[k] : k;
         ys[i] = (float)((yc[k] - mu) / sd);
       }
-      MB mb;
-      rc = step_grad(ps, b, sel.data(), Bsz, ys.data(), &mb);
+      P.add(b, sel.data(), Bsz, ys.data());
+    }
+    const int steps = P.steps();
+    if (steps == 0) {
+      if (loss_curve) loss_curve[ep] = 0.0f;
+      continue;
+    }
+    PlanDev D;
+    rc = upload_plan(ps, P, &D);
+    if (rc) return rc;
+    MB mb;
+    rc = alloc_ws(ps, Bsz, P.max_nn, true, &mb);
+    if (rc) return rc;
+    for (int s = 0; s < steps; ++s) {
+      bind_step(P, D, s, &mb);
+      rc = step_grad(ps, b, mb);
       if (rc) return rc;
       ps->step += 1;
       const float c1 = 1.0f - (float)std::pow(ps->cfg.beta1, (double)ps->step);
       const float c2 = 1.0f - (float)std::pow(ps->cfg.beta2, (double)ps->step);
-      hipLaunchKernelGGL(k_adam, dim3(nblk(P)), dim3(256), 0, c->stream, ps->w, ps->gr, ps->m, ps->v, P,
+      hipLaunchKernelGGL(k_adam, dim3(nblk(Pn)), dim3(256), 0, c->stream, ps->w, ps->gr, ps->m, ps->v, Pn,
                          (float)ps->cfg.lr, (float)ps->cfg.beta1, (float)ps->cfg.beta2, (float)ps->cfg.eps, c1, c2,
                          ps->wbf);
       PS_TRY(c, hipGetLastError());
-      float l = 0;
-      PS_TRY(c, hipMemcpyAsync(&l, mb.loss, 4, hipMemcpyDeviceToHost, c->stream));
-      PS_TRY(c, hipStreamSynchronize(c->stream));
-      lsum += l;
-      ++nb;
     }
-    if (loss_curve) loss_curve[ep] = nb ? (float)(lsum / nb) : 0.0f;
+    std::vector<float> losses(steps);
+    PS_TRY(c, hipMemcpyAsync(losses.data(), D.loss, (size_t)steps * 4, hipMemcpyDeviceToHost, c->stream));
+    PS_TRY(c, hipStreamSynchronize(c->stream));
+    double lsum = 0;
+    for (float l : losses) lsum += l;
+    if (loss_curve) loss_curve[ep] = (float)(lsum / steps);
   }
-  return AD_OK;
-}
-
-extern "C" int ad_prescreen_get_scale(ad_prescreen *ps, double *mean, double *sd) {
-  if (!ps) return AD_E_INVALID;
-  if (mean) *mean = ps->mean;
-  if (sd) *sd = ps->sd;
   return AD_OK;
 }
