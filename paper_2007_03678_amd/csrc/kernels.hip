@@ -34,11 +34,21 @@ __device__ __forceinline__ double dpp_f64(double v) {
   return __hiloint2double(hi, lo);
 }
 
+// row shift with bound_ctrl: lanes whose source lies outside the row read 0,
+// so no zeroed destination is needed
+template <int CTRL>
+__device__ __forceinline__ double dpp_shr_f64(double v) {
+  const int l = (int)__double2loint(v), h = (int)__double2hiint(v);
+  const int lo = __builtin_amdgcn_update_dpp(l, l, CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(h, h, CTRL, 0xf, 0xf, true);
+  return __hiloint2double(hi, lo);
+}
+
 __device__ __forceinline__ double wave_incl_scan(double v) {
-  v += dpp_f64<0x111, 0xf>(v);   // row_shr:1
-  v += dpp_f64<0x112, 0xf>(v);   // row_shr:2
-  v += dpp_f64<0x114, 0xf>(v);   // row_shr:4
-  v += dpp_f64<0x118, 0xf>(v);   // row_shr:8
+  v += dpp_shr_f64<0x111>(v);    // row_shr:1
+  v += dpp_shr_f64<0x112>(v);    // row_shr:2
+  v += dpp_shr_f64<0x114>(v);    // row_shr:4
+  v += dpp_shr_f64<0x118>(v);    // row_shr:8
   v += dpp_f64<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
   v += dpp_f64<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
   return v;
@@ -424,16 +434,12 @@ __device__ double evaluate(const EvalConst &C, const LaneLig<CAP> &LL, EvalLds<C
   extern __shared__ __attribute__((aligned(16))) char dyn_lds[];
   const LJRec *s_lj = reinterpret_cast<const LJRec *>(dyn_lds + st.off);
   const PairRec *s_pr = reinterpret_cast<const PairRec *>(dyn_lds + st.off + C.ff.n_types * C.ff.n_types * 16);
+  PairRec rec_next;
+  if (lane < L.n_pairs) rec_next = (STAGE && lane < st.n) ? s_pr[lane] : pr[lane];
   for (int p = lane; p < L.n_pairs; p += 64) {
-    PairRec rec;
-    LJRec lj;
-    if (STAGE && p < st.n) {
-      rec = s_pr[p];
-      lj = s_lj[rec.ijt >> 16];
-    } else {
-      rec = pr[p];
-      lj = STAGE ? s_lj[rec.ijt >> 16] : ljt[rec.ijt >> 16];
-    }
+    const PairRec rec = rec_next;
+    if (p + 64 < L.n_pairs) rec_next = (STAGE && p + 64 < st.n) ? s_pr[p + 64] : pr[p + 64];
+    const LJRec lj = STAGE ? s_lj[rec.ijt >> 16] : ljt[rec.ijt >> 16];
     const int i = rec.ijt & 0xff, j = (rec.ijt >> 8) & 0xff;
     const double dx = S.x[i][0] - S.x[j][0], dy = S.x[i][1] - S.x[j][1], dz = S.x[i][2] - S.x[j][2];
     const float r2 = (float)(dx * dx + dy * dy + dz * dz);
@@ -441,18 +447,26 @@ __device__ double evaluate(const EvalConst &C, const LaneLig<CAP> &LL, EvalLds<C
     e_intra += (double)pair_energy(C.ff, lj, rec.qq, rec.dsv, r2, &fs);
     if (GRAD) {
       const double f = (double)fs;
-      atomicAdd(&S.g[i][0], f * dx);
-      atomicAdd(&S.g[i][1], f * dy);
-      atomicAdd(&S.g[i][2], f * dz);
-      atomicAdd(&S.g[j][0], -f * dx);
-      atomicAdd(&S.g[j][1], -f * dy);
-      atomicAdd(&S.g[j][2], -f * dz);
+      const double fx = f * dx, fy = f * dy, fz = f * dz;
+      atomicAdd(&S.g[i][0], fx);
+      atomicAdd(&S.g[i][1], fy);
+      atomicAdd(&S.g[i][2], fz);
+      atomicAdd(&S.g[j][0], -fx);
+      atomicAdd(&S.g[j][1], -fy);
+      atomicAdd(&S.g[j][2], -fz);
     }
   }
-  const double inter = wave_sum(e_inter), intra = wave_sum(e_intra);
-  if (inter_out) *inter_out = inter;
-  if (intra_out) *intra_out = intra;
-  if (!GRAD) return inter + intra;
+  // one wavefront sum unless the caller wants the two parts
+  double total;
+  if (inter_out || intra_out) {
+    const double inter = wave_sum(e_inter), intra = wave_sum(e_intra);
+    if (inter_out) *inter_out = inter;
+    if (intra_out) *intra_out = intra;
+    total = inter + intra;
+  } else {
+    total = wave_sum(e_inter + e_intra);
+  }
+  if (!GRAD) return total;
   __syncthreads();
   // gradient back-projection: prefix sums over the internal atom order of
   // v_i = (g_i, (x_i - t) x g_i); each torsion's moving set is a range
@@ -509,7 +523,7 @@ __device__ double evaluate(const EvalConst &C, const LaneLig<CAP> &LL, EvalLds<C
     S.grad[7 + lane] = ux * tx + uy * ty + uz * tz;
   }
   __syncthreads();
-  return inter + intra;
+  return total;
 }
 
 __device__ __forceinline__ bool genotype_finite(const double *geno, int n_tor) {

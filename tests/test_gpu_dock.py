@@ -194,7 +194,10 @@ def test_dock_parameter_errors(pkg, setup):
     batch = ctx.ad_load_ligands([synth.ligand(60, 10, 2)])
     for kw, code in [(dict(pop=1), pkg.AD_E_INVALID), (dict(pop=5000), pkg.AD_E_INVALID),
                      (dict(ls_rate=1.5), pkg.AD_E_INVALID), (dict(rho=1.0), pkg.AD_E_INVALID),
-                     (dict(autostop=1), pkg.AD_E_UNSUPPORTED), (dict(ls_method=1), pkg.AD_E_UNSUPPORTED),
+                     (dict(autostop=2), pkg.AD_E_INVALID), (dict(ls_method=2), pkg.AD_E_UNSUPPORTED),
+                     (dict(ls_method=1, sw_rho=0.0), pkg.AD_E_INVALID),
+                     (dict(ls_method=1, sw_max_fail=0), pkg.AD_E_INVALID),
+                     (dict(autostop=1, stop_std=-1.0), pkg.AD_E_INVALID),
                      (dict(nrun=0), pkg.AD_E_INVALID)]:
         with pytest.raises(pkg.AddockError) as e:
             ctx.ad_dock_batch(batch, small_params(pkg, **kw), 1)
