@@ -39,6 +39,24 @@ def flops_per_eval(info, grad):
     return 36 * P + 84 * N + 18 * D + 22 * T + 40
 
 
+def measured_traffic():
+    """HBM bytes per launch of the local-search kernel from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None once the kernel
+    source differs from the one the counters were taken on."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_ls_generation_screen64.md")
+    src = os.path.join(ROOT, "paper_2007_03678_amd", "csrc", "kernels.hip")
+    try:
+        fields = dict(line.split(": ", 1) for line in open(path).read().splitlines()
+                      if line.startswith("traffic_"))
+        h = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if fields.get("traffic_kernel_sha256", "").strip() != h:
+            return None
+        return float(fields["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def workload(name, n_ligands=None):
     import synth
     c = synth.config(name, n_ligands=n_ligands)
@@ -319,7 +337,9 @@ def main():
             "peak": PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_TFLOPS, 4),
-            "traffic": None,
+            "traffic": measured_traffic(),
+            "traffic_note": "HBM (L2-to-fabric) bytes per launch from rocprofv3 FETCH_SIZE/WRITE_SIZE scaled by a "
+                            "1 GiB copy; null if the kernel changed since",
             "flop_per_launch": ls_flop,
             "avg_launch_ms": round(ls_avg_s * 1e3, 4),
             "ga_kernel_tflops": round(ga_flop / (ga_ms / 1e3 / max(ga_n, 1)) / 1e12, 3) if ga_n else None,
