@@ -149,6 +149,15 @@ int ad_ligand_check(const ad_ligand *lig, int n_types, char *msg, int msg_len);
  * no map.  The batch belongs to the caller until ad_free_batch, and stays
  * valid across grid reloads that keep the map types. */
 int ad_load_ligands(ad_ctx *ctx, int n, const ad_ligand *ligs, ad_batch **out);
+/* ad_load_ligands_packed: as ad_load_ligands for n ligands stored back to
+ * back (host arrays): ligand i has n_atoms[i] atoms and n_bonds[i] bonds;
+ * its atoms start at the sum of the earlier n_atoms in type_id, charge and
+ * xyz (3 floats per atom), its bonds at the sum of the earlier n_bonds in
+ * bonds (2 ints per bond) and rotatable.  Serves large synthetic sets
+ * without one host structure per ligand (Sec. 2.2.1: many ligands per run). */
+int ad_load_ligands_packed(ad_ctx *ctx, int n, const int *n_atoms, const int *n_bonds, const int *type_id,
+                           const float *charge, const float *xyz, const int *bonds, const unsigned char *rotatable,
+                           ad_batch **out);
 void ad_free_batch(ad_batch *b);
 /* Per-ligand sizes: atoms, torsions, intramolecular pairs, rigid fragments,
  * and depth_sum = sum over atoms of the number of torsions that move the

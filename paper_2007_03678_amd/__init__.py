@@ -25,7 +25,7 @@ ERR_NAMES = {0: "AD_OK", -1: "AD_E_INVALID", -2: "AD_E_NOMAP", -3: "AD_E_OOM", -
 MAX_TYPES, STRIDE = 16, 40
 
 EXPORTS = ["ad_create", "ad_destroy", "ad_last_error", "ad_set_stream", "ad_synchronize", "ad_load_grids",
-           "ad_build_grids", "ad_ligand_check", "ad_load_ligands", "ad_free_batch", "ad_batch_info",
+           "ad_build_grids", "ad_ligand_check", "ad_load_ligands", "ad_load_ligands_packed", "ad_free_batch", "ad_batch_info",
            "ad_score_poses", "ad_dock_batch", "ad_dock_select", "ad_local_search", "ad_solis_wets", "ad_initial_population",
            "ad_set_kernel_timing", "ad_get_kernel_timing", "ad_set_schedule", "ad_get_schedule",
            "ad_prescreen_n_params", "ad_prescreen_create",
@@ -139,6 +139,7 @@ def lib():
     L.ad_build_grids.argtypes = [vp, C.POINTER(GridDesc), C.c_int, fp, ip, fp, fp]
     L.ad_ligand_check.argtypes = [C.POINTER(Ligand), C.c_int, C.c_char_p, C.c_int]
     L.ad_load_ligands.argtypes = [vp, C.c_int, C.POINTER(Ligand), C.POINTER(vp)]
+    L.ad_load_ligands_packed.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp, vp, vp, C.POINTER(vp)]
     L.ad_free_batch.argtypes = [vp]
     L.ad_free_batch.restype = None
     L.ad_batch_info.argtypes = [vp, C.c_int, ip, ip, ip, ip, ip]
@@ -345,11 +346,26 @@ class Context:
         return out
 
     def ad_load_ligands(self, ligs) -> Batch:
+        if hasattr(ligs, "n_atoms_per_ligand"):   # a packed set (synth.LigandPack)
+            return self.ad_load_ligands_packed(ligs)
         arrs = [_LigandArrays(l) for l in ligs]
         arr = (Ligand * max(1, len(arrs)))(*[a.s for a in arrs])
         h = C.c_void_p()
         self._check(lib().ad_load_ligands(self.h, len(arrs), arr, C.byref(h)))
         return Batch(self, h, len(arrs))
+
+    def ad_load_ligands_packed(self, pack) -> Batch:
+        na = _np(pack.n_atoms_per_ligand, np.int32)
+        nb = _np(pack.n_bonds_per_ligand, np.int32)
+        ty = _np(pack.types, np.int32)
+        q = _np(pack.charges, np.float32)
+        xyz = _np(pack.xyz, np.float32).reshape(-1)
+        bd = _np(pack.bonds, np.int32).reshape(-1)
+        rot = _np(pack.rotatable, np.uint8)
+        h = C.c_void_p()
+        self._check(lib().ad_load_ligands_packed(self.h, len(na), _ptr(na), _ptr(nb), _ptr(ty), _ptr(q), _ptr(xyz),
+                                                 _ptr(bd), _ptr(rot), C.byref(h)))
+        return Batch(self, h, len(na))
 
     def ad_score_poses(self, batch, lig_idx, genotypes, grad=False, terms=False, out=None):
         """Host (numpy) or device (torch CUDA) arrays.  Returns (energy, grad, terms)."""

@@ -4,6 +4,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <thread>
+
 #include <algorithm>
 #include <cmath>
 #include <string>
@@ -31,6 +33,24 @@ int ad_ctx::hip_fail(hipError_t e, const char *where) {
     hipError_t _e = (expr);                                 \
     if (_e != hipSuccess) return (ctx)->hip_fail(_e, #expr); \
   } while (0)
+
+// fn(i) for i in [0, n) on up to 16 host threads (contiguous blocks)
+template <typename F>
+void parallel_for(int n, F fn) {
+  const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+  const int nt = std::min({hw, 16, std::max(1, n / 64)});
+  if (nt <= 1) {
+    for (int i = 0; i < n; ++i) fn(i);
+    return;
+  }
+  std::vector<std::thread> th;
+  for (int t = 0; t < nt; ++t)
+    th.emplace_back([&, t]() {
+      const int lo = (int)((long long)n * t / nt), hi = (int)((long long)n * (t + 1) / nt);
+      for (int i = lo; i < hi; ++i) fn(i);
+    });
+  for (auto &x : th) x.join();
+}
 
 void *ad_ctx::scratch_alloc(size_t bytes, int slot) {
   // per-slot grow-only device buffers; calls on one context are serialised
@@ -333,12 +353,14 @@ extern "C" int ad_load_ligands(ad_ctx *c, int n, const ad_ligand *ligs, ad_batch
   *out = nullptr;
   if (n < 0 || (n > 0 && !ligs)) return c->fail(AD_E_INVALID, "bad ligand array");
   if (!c->has_grid) return c->fail(AD_E_STATE, "load or build grids before ligands");
+  // host preparation (validation, torsion tree, pair list, features) runs on
+  // all host threads; the first failing ligand (lowest index) is reported
   std::vector<PreparedLigand> prep(n);
-  for (int i = 0; i < n; ++i) {
-    std::string err;
-    int rc = prepare_ligand(ligs[i], c->ff, c->type_to_map, &prep[i], &err);
-    if (rc) return c->fail(rc, "ligand " + std::to_string(i) + ": " + err);
-  }
+  std::vector<int> prep_rc(n, AD_OK);
+  std::vector<std::string> prep_err(n);
+  parallel_for(n, [&](int i) { prep_rc[i] = prepare_ligand(ligs[i], c->ff, c->type_to_map, &prep[i], &prep_err[i]); });
+  for (int i = 0; i < n; ++i)
+    if (prep_rc[i]) return c->fail(prep_rc[i], "ligand " + std::to_string(i) + ": " + prep_err[i]);
   ad_batch *b = new ad_batch();
   b->ctx = c;
   b->uid = c->next_batch_uid++;
@@ -380,18 +402,24 @@ extern "C" int ad_load_ligands(ad_ctx *c, int n, const ad_ligand *ligs, ad_batch
     if (bytes && hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice) != hipSuccess) return false;
     return true;
   };
+  std::vector<std::vector<uint16_t>> fx(n);
+  std::vector<std::vector<uint8_t>> fn(n);
+  std::vector<char> f_ok(n, 1);
+  parallel_for(n, [&](int i) {
+    if (!featurize(ligs[i], prep[i].perm, &fx[i], &fn[i])) {
+      f_ok[i] = 0;
+      fx[i].assign((size_t)prep[i].n_atoms * kFeat, 0);
+      fn[i].assign((size_t)prep[i].n_atoms * kMaxDeg, 0xff);
+    }
+  });
   std::vector<uint16_t> psx;
   std::vector<uint8_t> psn;
+  psx.reserve(geo.size() * kFeat);
+  psn.reserve(geo.size() * kMaxDeg);
   for (int i = 0; i < n; ++i) {
-    std::vector<uint16_t> x1;
-    std::vector<uint8_t> n1;
-    if (!featurize(ligs[i], prep[i].perm, &x1, &n1)) {
-      b->ps_ok = false;
-      x1.assign((size_t)prep[i].n_atoms * kFeat, 0);
-      n1.assign((size_t)prep[i].n_atoms * kMaxDeg, 0xff);
-    }
-    psx.insert(psx.end(), x1.begin(), x1.end());
-    psn.insert(psn.end(), n1.begin(), n1.end());
+    if (!f_ok[i]) b->ps_ok = false;
+    psx.insert(psx.end(), fx[i].begin(), fx[i].end());
+    psn.insert(psn.end(), fn[i].begin(), fn[i].end());
   }
   b->n_atoms_total = (int)geo.size();
   bool ok = up((void **)&b->ps_x, psx.data(), psx.size() * sizeof(uint16_t)) &&
@@ -407,6 +435,31 @@ extern "C" int ad_load_ligands(ad_ctx *c, int n, const ad_ligand *ligs, ad_batch
   }
   *out = b;
   return AD_OK;
+}
+
+extern "C" int ad_load_ligands_packed(ad_ctx *c, int n, const int *n_atoms, const int *n_bonds, const int *type_id,
+                                      const float *charge, const float *xyz, const int *bonds,
+                                      const unsigned char *rotatable, ad_batch **out) {
+  if (!c || !out) return AD_E_INVALID;
+  *out = nullptr;
+  if (n < 0 || (n > 0 && (!n_atoms || !n_bonds || !type_id || !charge || !xyz)))
+    return c->fail(AD_E_INVALID, "bad packed ligand arrays");
+  std::vector<ad_ligand> v(n);
+  size_t a = 0, bo = 0;
+  for (int i = 0; i < n; ++i) {
+    if (n_atoms[i] < 1 || n_bonds[i] < 0) return c->fail(AD_E_INVALID, "ligand " + std::to_string(i) + ": bad counts");
+    if (n_bonds[i] > 0 && (!bonds || !rotatable)) return c->fail(AD_E_INVALID, "null bond arrays");
+    v[i].n_atoms = n_atoms[i];
+    v[i].n_bonds = n_bonds[i];
+    v[i].type_id = type_id + a;
+    v[i].charge = charge + a;
+    v[i].xyz = xyz + 3 * a;
+    v[i].bonds = n_bonds[i] ? bonds + 2 * bo : nullptr;
+    v[i].rotatable = n_bonds[i] ? rotatable + bo : nullptr;
+    a += (size_t)n_atoms[i];
+    bo += (size_t)n_bonds[i];
+  }
+  return ad_load_ligands(c, n, v.data(), out);
 }
 
 extern "C" void ad_free_batch(ad_batch *b) {

@@ -17,6 +17,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "api_internal.h"
 
 namespace ad {
@@ -1235,20 +1237,37 @@ hipError_t launch_relayout(const float *soa, float *out4, size_t nn, int n_maps,
 }
 
 
+// A 1-D grid holds fewer than 2^31 work-items: very large batches are
+// launched in chunks of runs (the kernels find their run through run_order).
+template <typename F>
+hipError_t for_run_chunks(const DockArgs &D, int blocks_per_run, F launch) {
+  const long long max_blocks = ((1LL << 31) - 64) / 64;
+  const int step = (int)std::max(1LL, max_blocks / std::max(1, blocks_per_run));
+  for (int r0 = 0; r0 < D.n_launch; r0 += step) {
+    DockArgs Dc = D;
+    Dc.run_order = D.run_order + r0;
+    Dc.n_launch = std::min(step, D.n_launch - r0);
+    launch(Dc, dim3((unsigned)((long long)Dc.n_launch * blocks_per_run)));
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t launch_dock_init(const EvalConst &C, int cap, const DockArgs &D, hipStream_t s) {
   if (D.n_launch <= 0) return hipSuccess;
-  dim3 grid((unsigned)D.n_launch * D.pop), block(64);
-  if (cap <= 64) hipLaunchKernelGGL((k_init_pop<64>), grid, block, 0, s, C, D);
-  else hipLaunchKernelGGL((k_init_pop<128>), grid, block, 0, s, C, D);
-  return hipGetLastError();
+  return for_run_chunks(D, D.pop, [&](const DockArgs &Dc, dim3 grid) {
+    if (cap <= 64) hipLaunchKernelGGL((k_init_pop<64>), grid, dim3(64), 0, s, C, Dc);
+    else hipLaunchKernelGGL((k_init_pop<128>), grid, dim3(64), 0, s, C, Dc);
+  });
 }
 
 hipError_t launch_ga_generation(const EvalConst &C, int cap, const DockArgs &D, int gen, hipStream_t s) {
   if (D.n_launch <= 0) return hipSuccess;
-  dim3 grid((unsigned)D.n_launch * D.pop), block(64);
-  if (cap <= 64) hipLaunchKernelGGL((k_ga_generation<64>), grid, block, 0, s, C, D, gen);
-  else hipLaunchKernelGGL((k_ga_generation<128>), grid, block, 0, s, C, D, gen);
-  return hipGetLastError();
+  return for_run_chunks(D, D.pop, [&](const DockArgs &Dc, dim3 grid) {
+    if (cap <= 64) hipLaunchKernelGGL((k_ga_generation<64>), grid, dim3(64), 0, s, C, Dc, gen);
+    else hipLaunchKernelGGL((k_ga_generation<128>), grid, dim3(64), 0, s, C, Dc, gen);
+  });
 }
 
 size_t ls_dynamic_lds(const EvalConst &C, const DockArgs &D) {
@@ -1258,23 +1277,21 @@ size_t ls_dynamic_lds(const EvalConst &C, const DockArgs &D) {
 
 hipError_t launch_ls_generation(const EvalConst &C, int cap, const DockArgs &D, int gen, hipStream_t s) {
   if (D.n_launch <= 0 || D.n_ls <= 0) return hipSuccess;
-  dim3 block(64);
-  dim3 lgrid((unsigned)D.n_launch * D.n_ls);
+  const dim3 block(64);
   const size_t dyn = ls_dynamic_lds(C, D);
-  if (D.ls_method == 1) {
-    if (cap <= 64) hipLaunchKernelGGL((k_sw_generation<64>), lgrid, block, (size_t)D.pop * sizeof(int), s, C, D, gen);
-    else hipLaunchKernelGGL((k_sw_generation<128>), lgrid, block, (size_t)D.pop * sizeof(int), s, C, D, gen);
-    return hipGetLastError();
-  }
   const bool st = D.stage_pairs > 0;
-  if (cap <= 64) {
-    if (st) hipLaunchKernelGGL((k_ls_generation<64, true>), lgrid, block, dyn, s, C, D, gen);
-    else hipLaunchKernelGGL((k_ls_generation<64, false>), lgrid, block, dyn, s, C, D, gen);
-  } else {
-    if (st) hipLaunchKernelGGL((k_ls_generation<128, true>), lgrid, block, dyn, s, C, D, gen);
-    else hipLaunchKernelGGL((k_ls_generation<128, false>), lgrid, block, dyn, s, C, D, gen);
-  }
-  return hipGetLastError();
+  return for_run_chunks(D, D.n_ls, [&](const DockArgs &Dc, dim3 lgrid) {
+    if (D.ls_method == 1) {
+      if (cap <= 64) hipLaunchKernelGGL((k_sw_generation<64>), lgrid, block, (size_t)D.pop * sizeof(int), s, C, Dc, gen);
+      else hipLaunchKernelGGL((k_sw_generation<128>), lgrid, block, (size_t)D.pop * sizeof(int), s, C, Dc, gen);
+    } else if (cap <= 64) {
+      if (st) hipLaunchKernelGGL((k_ls_generation<64, true>), lgrid, block, dyn, s, C, Dc, gen);
+      else hipLaunchKernelGGL((k_ls_generation<64, false>), lgrid, block, dyn, s, C, Dc, gen);
+    } else {
+      if (st) hipLaunchKernelGGL((k_ls_generation<128, true>), lgrid, block, dyn, s, C, Dc, gen);
+      else hipLaunchKernelGGL((k_ls_generation<128, false>), lgrid, block, dyn, s, C, Dc, gen);
+    }
+  });
 }
 
 hipError_t launch_solis_wets(const EvalConst &C, int cap, const DockArgs &D, int n, const int *lig_idx, float *geno,

@@ -379,11 +379,51 @@ def _ligen_lib():
     return _ligen
 
 
+@dataclass
+class LigandPack:
+    """Ligands stored back to back: ligand i owns n_atoms_per_ligand[i] atoms
+    and n_bonds_per_ligand[i] bonds, in order."""
+    n_atoms_per_ligand: np.ndarray   # [n] int32
+    n_bonds_per_ligand: np.ndarray   # [n] int32
+    types: np.ndarray                # [sum atoms] int32
+    charges: np.ndarray              # [sum atoms] float32
+    xyz: np.ndarray                  # [sum atoms, 3] float32
+    bonds: np.ndarray                # [sum bonds, 2] int32 (indices local to the ligand)
+    rotatable: np.ndarray            # [sum bonds] uint8
+
+    def __len__(self):
+        return len(self.n_atoms_per_ligand)
+
+    def __getitem__(self, i) -> Ligand:
+        return self.ligands([i])[0]
+
+    def ligands(self, idx=None) -> list:
+        """Ligand objects (views) for the given indices (default: all)."""
+        ao = np.concatenate([[0], np.cumsum(self.n_atoms_per_ligand)])
+        bo = np.concatenate([[0], np.cumsum(self.n_bonds_per_ligand)])
+        sel = range(len(self)) if idx is None else idx
+        return [Ligand(self.types[ao[i]:ao[i + 1]], self.charges[ao[i]:ao[i + 1]], self.xyz[ao[i]:ao[i + 1]],
+                       self.bonds[bo[i]:bo[i + 1]], self.rotatable[bo[i]:bo[i + 1]]) for i in sel]
+
+    def subset(self, idx) -> "LigandPack":
+        return pack_ligands(self.ligands(idx))
+
+
+def pack_ligands(ligs) -> LigandPack:
+    return LigandPack(np.array([l.n_atoms for l in ligs], np.int32), np.array([len(l.bonds) for l in ligs], np.int32),
+                      np.concatenate([l.types for l in ligs]).astype(np.int32),
+                      np.concatenate([l.charges for l in ligs]).astype(np.float32),
+                      np.concatenate([l.xyz for l in ligs]).astype(np.float32),
+                      np.concatenate([np.asarray(l.bonds).reshape(-1, 2) for l in ligs]).astype(np.int32),
+                      np.concatenate([l.rotatable for l in ligs]).astype(np.uint8))
+
+
 def ligand_set_fast(seed: int, n_ligands: int, atoms=(10, 100), torsions=(0, 32), dist="lognormal",
-                    freqs=FREQ_SIX, min_nonlocal: float = 2.0) -> list:
+                    freqs=FREQ_SIX, min_nonlocal: float = 2.0, packed: bool = False):
     """Like ligand_set, generated by the C generator (about 10^5 ligands/s on
     8 cores).  Sizes and torsion requests are drawn here with numpy from
-    `seed`; ligand i is grown from seed * 2^20 + i."""
+    `seed`; ligand i is grown from seed * 2^20 + i.  packed=True returns a
+    LigandPack (the same ligands back to back) instead of a list."""
     rng = np.random.default_rng(np.random.PCG64(seed))
     if dist == "uniform":
         n = rng.integers(atoms[0], atoms[1] + 1, size=n_ligands)
@@ -407,6 +447,8 @@ def ligand_set_fast(seed: int, n_ligands: int, atoms=(10, 100), torsions=(0, 32)
                                     xyz.ctypes.data, bonds.ctypes.data, rot.ctypes.data)
     if rc:
         raise RuntimeError(f"C ligand generator failed on ligand {-rc - 1}")
+    if packed:
+        return LigandPack(n, np.maximum(n - 1, 0).astype(np.int32), types, q, xyz, bonds[:nb], rot[:nb])
     out = []
     a = b = 0
     for i in range(n_ligands):
@@ -463,7 +505,8 @@ def config(name: str, seed: int = 20200707, n_ligands: int | None = None) -> dic
 
     single24:  1 ligand, N=24, T=5; 2,000-atom receptor in a 20 A cube; 40^3 grid, 6 type maps.
     screen64:  64 ligands, N~U[15,60], T~U[0,15]; 8,000-atom receptor; 64^3 grid, 8 type maps.
-    batch4096: 4,096 ligands, N lognormal (median 32) in [10,100], T~U[0,32]; 80^3 grid.
+    batch4096: 4,096 ligands, N lognormal (median 32) in [10,100], T~U[0,32]; 80^3 grid
+               (ligands from the C generator, as a LigandPack).
     campaign:  ligands as batch4096 on a 126^3 grid.
     """
     if name == "single24":
@@ -479,14 +522,14 @@ def config(name: str, seed: int = 20200707, n_ligands: int | None = None) -> dic
     elif name == "batch4096":
         rec = receptor(seed, 8000)
         grid = make_grid(80, 0.375, map_types=ALL_TYPES)
-        ligs = ligand_set(seed + 1, n_ligands or 4096, atoms=(10, 100), torsions=(0, 32),
-                          dist="lognormal")
+        ligs = ligand_set_fast(seed + 1, n_ligands or 4096, atoms=(10, 100), torsions=(0, 32),
+                               dist="lognormal", packed=True)
         dock = dict(nrun=10, pop=150, max_gens=10**9, max_evals=100_000, ls_rate=0.06, ls_iters=300)
     elif name == "campaign":
         rec = receptor(seed, 8000)
         grid = make_grid(126, 0.375, map_types=ALL_TYPES)
-        ligs = ligand_set(seed + 1, n_ligands or 65536, atoms=(10, 100), torsions=(0, 32),
-                          dist="lognormal")
+        ligs = ligand_set_fast(seed + 1, n_ligands or 65536, atoms=(10, 100), torsions=(0, 32),
+                               dist="lognormal", packed=True)
         dock = dict(nrun=20, pop=150, max_gens=10**9, max_evals=2_500_000, ls_rate=0.06, ls_iters=300)
     else:
         raise KeyError(name)

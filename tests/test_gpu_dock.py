@@ -189,6 +189,30 @@ def test_schedules_give_identical_results(pkg, setup):
         batch.free()
 
 
+def test_packed_loading_docks_the_same(pkg, setup):
+    """Ligands loaded back to back (ad_load_ligands_packed) prepare and dock
+    bitwise as the same ligands loaded one structure each."""
+    ctx, grid, G = setup
+    pack = synth.ligand_set_fast(31, 6, atoms=(10, 90), torsions=(0, 24), packed=True)
+    a = ctx.ad_load_ligands(pack.ligands())
+    b = ctx.ad_load_ligands_packed(pack)
+    try:
+        assert a.n == b.n == 6
+        for i in range(6):
+            assert a.info(i) == b.info(i)
+        p = small_params(pkg, ls_iters=20, max_gens=3)
+        ra, rb = (ctx.ad_dock_batch(x, p, 5, per_run=True) for x in (a, b))
+        for k in ("run_energy", "run_genotype", "evals"):
+            assert np.array_equal(ra[k], rb[k]), k
+    finally:
+        a.free()
+        b.free()
+    with pytest.raises(pkg.AddockError):
+        bad = synth.pack_ligands(pack.ligands([0, 1]))
+        bad.n_atoms_per_ligand[1] = 0
+        ctx.ad_load_ligands_packed(bad)
+
+
 def test_dock_parameter_errors(pkg, setup):
     ctx, grid, G = setup
     batch = ctx.ad_load_ligands([synth.ligand(60, 10, 2)])

@@ -81,6 +81,22 @@ def test_fast_ligand_set_is_valid_and_seeded():
     assert not all(np.array_equal(a.types, b.types) for a, b in zip(L, other))
 
 
+def test_packed_ligand_set_matches_the_list():
+    L = synth.ligand_set_fast(6, 400)
+    P = synth.ligand_set_fast(6, 400, packed=True)
+    assert len(P) == 400 and P.n_atoms_per_ligand.sum() == len(P.types) == len(P.xyz)
+    assert P.n_bonds_per_ligand.sum() == len(P.bonds) == len(P.rotatable)
+    for i in (0, 1, 199, 399):
+        a, b = L[i], P[i]
+        assert np.array_equal(a.types, b.types) and np.array_equal(a.xyz, b.xyz)
+        assert np.array_equal(a.charges, b.charges) and np.array_equal(a.bonds, b.bonds)
+        assert np.array_equal(a.rotatable, b.rotatable)
+    S = P.subset([7, 3])
+    assert np.array_equal(S[0].xyz, L[7].xyz) and np.array_equal(S[1].bonds, L[3].bonds)
+    R = synth.pack_ligands(L[:50])
+    assert np.array_equal(R.xyz, P.xyz[:R.n_atoms_per_ligand.sum()])
+
+
 def test_fast_ligand_type_frequencies():
     L = synth.ligand_set_fast(9, 2000, atoms=(20, 40), dist="uniform")
     t = np.concatenate([l.types for l in L])
