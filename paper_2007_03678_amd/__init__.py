@@ -35,7 +35,10 @@ EXPORTS = ["ad_create", "ad_destroy", "ad_last_error", "ad_set_stream", "ad_sync
 
 def build(verbose: bool = False, arch: str = "gfx950") -> str:
     """Compile libaddock.so in-tree with hipcc for gfx950 (always recompiles)."""
-    cmd = ["hipcc", f"--offload-arch={arch}", "-O3", "-std=c++17", "-fPIC", "-shared",
+    # -ffp-contract=on: a*b+c is fused only within one source expression, so
+    # every instantiation of the evaluation (with or without the gradient)
+    # rounds the energy the same way and a returned pose re-scores bitwise
+    cmd = ["hipcc", f"--offload-arch={arch}", "-O3", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=on",
            "-Wno-unused-result", "-Wno-unused-value",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
     cmd += [os.path.join(HERE, s) for s in SOURCES] + ["-o", LIB_PATH + ".tmp"]

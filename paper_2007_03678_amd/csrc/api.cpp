@@ -389,6 +389,7 @@ extern "C" int ad_load_ligands(ad_ctx *c, int n, const ad_ligand *ligs, ad_batch
     tors.insert(tors.end(), P.tors.begin(), P.tors.end());
     if (P.n_atoms > 64) cap = 128;
   }
+  pairs.resize(pairs.size() + kWave, PairRec{0, 0.0f, 0.0f, 0.0f});   // spare records: the kernels prefetch 64 ahead
   b->cap = cap;
   b->lig_host = lig;
   b->depth_sum.resize(n);

@@ -242,7 +242,8 @@ struct LaneLig {
 };
 
 // Trilinear interpolation of map_m + q map_e + |q| map_d with its gradient,
-// plus the out-of-box restraint.  FP64.
+// plus the out-of-box restraint.  FP64 (near the map cap the corner values
+// are ~1e5 while their differences, the gradient, are small).
 __device__ __forceinline__ double grid_energy(const GridArgs &G, double k_out, int m, float qf, const double x[3],
                                               double g[3]) {
   const double q = qf, aq = fabs(q);
@@ -269,20 +270,18 @@ __device__ __forceinline__ double grid_energy(const GridArgs &G, double k_out, i
   for (int c = 0; c < 8; ++c) {
     size_t off = base + ((c & 1) ? sx : 0) + ((c & 2) ? sy : 0) + ((c & 4) ? sz : 0);
     const float4 r = M[off];
-    v[c] = (double)r.x + q * (double)r.y + aq * (double)r.z;
+    v[c] = fma(aq, (double)r.z, fma(q, (double)r.y, (double)r.x));
   }
   const double fx = f[0], fy = f[1], fz = f[2];
-  const double gx = 1.0 - fx, gy = 1.0 - fy, gz = 1.0 - fz;
-  // along x
-  double a00 = v[0] * gx + v[1] * fx, a10 = v[2] * gx + v[3] * fx;
-  double a01 = v[4] * gx + v[5] * fx, a11 = v[6] * gx + v[7] * fx;
-  double b0 = a00 * gy + a10 * fy, b1 = a01 * gy + a11 * fy;
-  double E = b0 * gz + b1 * fz;
-  double dx00 = v[1] - v[0], dx10 = v[3] - v[2], dx01 = v[5] - v[4], dx11 = v[7] - v[6];
-  double dEdu0 = ((dx00 * gy + dx10 * fy) * gz + (dx01 * gy + dx11 * fy) * fz);
-  double dEdu1 = ((a10 - a00) * gz + (a11 - a01) * fz);
-  double dEdu2 = (b1 - b0);
-  double dEdu[3] = {dEdu0, dEdu1, dEdu2};
+  // along x (corner c: bit 0 = x, bit 1 = y, bit 2 = z), then y, then z
+  const double d00 = v[1] - v[0], d10 = v[3] - v[2], d01 = v[5] - v[4], d11 = v[7] - v[6];
+  const double a00 = fma(fx, d00, v[0]), a10 = fma(fx, d10, v[2]);
+  const double a01 = fma(fx, d01, v[4]), a11 = fma(fx, d11, v[6]);
+  const double e0 = a10 - a00, e1 = a11 - a01;
+  const double b0 = fma(fy, e0, a00), b1 = fma(fy, e1, a01);
+  const double c0 = fma(fy, d10 - d00, d00), c1 = fma(fy, d11 - d01, d01);
+  double E = fma(fz, b1 - b0, b0);
+  const double dEdu[3] = {fma(fz, c1 - c0, c0), fma(fz, e1 - e0, e0), b1 - b0};
   const double o[3] = {G.ox, G.oy, G.oz};
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
@@ -301,12 +300,12 @@ __device__ __forceinline__ double grid_energy(const GridArgs &G, double k_out, i
 __device__ __forceinline__ float pair_energy(const FFConst &K, const LJRec &lj, float qq, float dsv, float r2,
                                              float *fscale) {
   const bool floored = !(r2 >= K.r_floor2);
-  const float r2c = floored ? K.r_floor2 : r2;
+  const float r2c = fmaxf(r2, K.r_floor2);   // NaN -> the floor, as the comparison above
   const float inv_r = fast_rsq(r2c);
   const float r = r2c * inv_r;
   // smoothed 12-6 / 12-10
   const float dr = r - lj.r0;
-  const float sh = fminf(fmaxf(dr, -K.half_smooth), K.half_smooth);
+  const float sh = __builtin_amdgcn_fmed3f(dr, -K.half_smooth, K.half_smooth);
   const float rr = r - sh;
   const float slope = fabsf(dr) > K.half_smooth ? 1.0f : 0.0f;
   const float inv = fast_rcp(rr);
@@ -429,7 +428,7 @@ __device__ double evaluate(const EvalConst &C, const LaneLig<CAP> &LL, EvalLds<C
     }
   }
   __syncthreads();
-  // intramolecular pairs
+  // intramolecular pairs, 64 per step in list order
   double e_intra = 0.0;
   const PairRec *pr = C.batch.pairs + L.pair_off;
   const LJRec *ljt = C.batch.lj;
@@ -440,7 +439,9 @@ __device__ double evaluate(const EvalConst &C, const LaneLig<CAP> &LL, EvalLds<C
   if (lane < L.n_pairs) rec_next = (STAGE && lane < st.n) ? s_pr[lane] : pr[lane];
   for (int p = lane; p < L.n_pairs; p += 64) {
     const PairRec rec = rec_next;
-    if (p + 64 < L.n_pairs) rec_next = (STAGE && p + 64 < st.n) ? s_pr[p + 64] : pr[p + 64];
+    // the batch's pair array ends with 64 spare records, so this prefetch
+    // stays in bounds; past the ligand's list it reads a record not used
+    rec_next = (STAGE && p + 64 < st.n) ? s_pr[p + 64] : pr[p + 64];
     const LJRec lj = STAGE ? s_lj[rec.ijt >> 16] : ljt[rec.ijt >> 16];
     const int i = rec.ijt & 0xff, j = (rec.ijt >> 8) & 0xff;
     const double dx = S.x[i][0] - S.x[j][0], dy = S.x[i][1] - S.x[j][1], dz = S.x[i][2] - S.x[j][2];
@@ -604,15 +605,15 @@ __device__ void adadelta_wave(const EvalConst &C, const LaneLig<CAP> &LL, EvalLd
     }
     Eg2 = (rho_d + zd) * Eg2 + (1.0 - (rho_d + zd)) * gd * gd;
     const float rg = fast_rsq((float)(Eg2 + eps_d));
-    const float dx = dof ? -__builtin_sqrtf(Edx2 + eps) * rg * (float)gd : 0.0f;
+    const float dx = dof ? -__builtin_amdgcn_sqrtf(Edx2 + eps) * rg * (float)gd : 0.0f;
     Edx2 = rho * Edx2 + (1.0f - rho) * dx * dx;
     // orientation: q <- exp(dw/2) (x) q from the three rotation lanes
     const float w0 = lane_f32(dx, 3), w1 = lane_f32(dx, 4), w2 = lane_f32(dx, 5);
     const float qw = lane_f32(gene, 3), qx = lane_f32(gene, 4), qy = lane_f32(gene, 5), qz = lane_f32(gene, 6);
-    const float th = __builtin_sqrtf(w0 * w0 + w1 * w1 + w2 * w2);
+    const float th = __builtin_amdgcn_sqrtf(w0 * w0 + w1 * w1 + w2 * w2);
     float sh, ch;
     __sincosf(0.5f * th, &sh, &ch);
-    const float f = th > 1e-30f ? sh / th : 0.5f;
+    const float f = th > 1e-30f ? sh * fast_rcp(th) : 0.5f;
     const float rx = f * w0, ry = f * w1, rz = f * w2;
     float nw = ch * qw - rx * qx - ry * qy - rz * qz;
     float nx = ch * qx + rx * qw + ry * qz - rz * qy;
