@@ -141,6 +141,7 @@ def batch_leg(args, log_fn):
         "generations": int(r["generations"][0]),
         "buckets": {"le64_atoms": batch.n - big, "le128_atoms": big},
         "ls_stage_pairs": sched["stage_pairs"],
+        "packed_runs": sched["packed_runs"],
         "ls_phase_avg_ms": round(ls_ms / max(ls_n, 1), 3),
         "ls_phase_tflops": round(ls_flop / (ls_ms / 1e3 / max(ls_n, 1)) / 1e12, 3) if ls_n else None,
     }
@@ -398,7 +399,8 @@ def main():
         },
     }
     # score-grad evaluations per second inside the local-search kernel
-    out["schedule"] = {"timed_steps": {"graph": schedule["graph"], "ls_stage_pairs": schedule["stage_pairs"]},
+    out["schedule"] = {"timed_steps": {"graph": schedule["graph"], "ls_stage_pairs": schedule["stage_pairs"],
+                                       "packed_runs": schedule["packed_runs"]},
                        "graph_replay_ms_per_step": round(graph_ms, 2), "graph": schedule_graph["graph"]}
     out["score_grad_evals_per_s"] = round(dock["nrun"] * n_lig * n_ls * dock["ls_iters"] / ls_avg_s, 1)
     batch.free()

@@ -281,12 +281,20 @@ int ad_initial_population(ad_ctx *ctx, const ad_batch *b, int lig, uint32_t lig_
  * stage_pairs pair records of each ligand in LDS; with autotune the size is
  * chosen per bucket by timing short local searches on a copy of the initial
  * population (cached per batch and shape), with stage_pairs >= 0 it is
- * forced (rounded down to a candidate: 0, 128, 256, 512, 1024, 2048).  Every
- * schedule computes identical results.  Defaults: graph on, autotune on. */
-int ad_set_schedule(ad_ctx *ctx, int use_graph, int autotune, int stage_pairs);
+ * forced (rounded down to a candidate: 0, 128, 256, 512, 1024, 2048).  With
+ * pack_small the ADADELTA local search of ligands of at most 32 atoms and 25
+ * torsions runs two individuals per wavefront (one per half), in the same
+ * launch as the 64-atom bucket's other runs, which then stage no pairs; the
+ * reported run energies are re-scored by the one-wavefront evaluation.
+ * Graph, autotune and staging change the speed only; packing sums a pose's
+ * energy in another order inside the search (the searches of packed
+ * ligands differ from unpacked ones at rounding level).  Defaults: graph on,
+ * autotune on, pack_small on. */
+int ad_set_schedule(ad_ctx *ctx, int use_graph, int autotune, int stage_pairs, int pack_small);
 /* stage_pairs[2]: the staging size used per bucket by the last dock call
- * (-1: bucket empty or no local search); graph_used: 1 if it ran as a graph. */
-int ad_get_schedule(ad_ctx *ctx, int *stage_pairs, int *graph_used);
+ * (-1: bucket empty or no local search); graph_used: 1 if it ran as a graph;
+ * packed_runs: runs whose local search was packed (any may be null). */
+int ad_get_schedule(ad_ctx *ctx, int *stage_pairs, int *graph_used, int *packed_runs);
 
 /* ---- diagnostics ----------------------------------------------------------
  * Kernel timing with HIP events recorded on the context's stream around

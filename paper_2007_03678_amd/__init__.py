@@ -155,8 +155,8 @@ def lib():
     L.ad_local_search.argtypes = [vp, vp, C.c_int, vp, vp, vp, C.POINTER(DockParams), C.c_int, C.c_int]
     L.ad_solis_wets.argtypes = [vp, vp, C.c_int, vp, vp, vp, vp, C.POINTER(DockParams), C.c_int, C.c_uint64]
     L.ad_initial_population.argtypes = [vp, vp, C.c_int, C.c_uint32, C.c_int, C.c_int, C.c_uint64, fp]
-    L.ad_set_schedule.argtypes = [vp, C.c_int, C.c_int, C.c_int]
-    L.ad_get_schedule.argtypes = [vp, ip, ip]
+    L.ad_set_schedule.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int]
+    L.ad_get_schedule.argtypes = [vp, ip, ip, ip]
     L.ad_prescreen_n_params.argtypes = []
     L.ad_prescreen_create.argtypes = [vp, C.POINTER(PrescreenCfg), C.c_uint64, C.POINTER(vp)]
     L.ad_prescreen_destroy.argtypes = [vp]
@@ -310,14 +310,14 @@ class Context:
         self._check(lib().ad_get_kernel_timing(self.h, C.byref(t), 1 if reset else 0))
         return {k: (t.ms[i], int(t.launches[i])) for i, k in enumerate(KERNEL_KINDS)}
 
-    def ad_set_schedule(self, use_graph=True, autotune=True, stage_pairs=-1):
-        self._check(lib().ad_set_schedule(self.h, int(use_graph), int(autotune), int(stage_pairs)))
+    def ad_set_schedule(self, use_graph=True, autotune=True, stage_pairs=-1, pack_small=True):
+        self._check(lib().ad_set_schedule(self.h, int(use_graph), int(autotune), int(stage_pairs), int(pack_small)))
 
     def ad_get_schedule(self):
         st = (C.c_int * 2)()
-        g = C.c_int()
-        self._check(lib().ad_get_schedule(self.h, st, C.byref(g)))
-        return dict(stage_pairs=[st[0], st[1]], graph=bool(g.value))
+        g, pk = C.c_int(), C.c_int()
+        self._check(lib().ad_get_schedule(self.h, st, C.byref(g), C.byref(pk)))
+        return dict(stage_pairs=[st[0], st[1]], graph=bool(g.value), packed_runs=pk.value)
 
     def ad_synchronize(self):
         self._check(lib().ad_synchronize(self.h))

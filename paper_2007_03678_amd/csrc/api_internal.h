@@ -43,6 +43,8 @@ struct DockArgs {
   int n_runs, nrun, pop, n_ls, ls_iters;
   int n_launch;      // runs covered by a launch: run_order[0..n_launch)
   int stage_pairs;   // local search: pair records staged in LDS per ligand (0: none)
+  int n_dual;        // ADADELTA: the first n_dual runs of run_order (whole ligands of at most
+                     // kDualAtoms atoms and kDualTor torsions) take the two-per-wavefront kernel
   // Solis-Wets local search
   int ls_method;     // 0 ADADELTA, 1 Solis-Wets
   float sw_rho, sw_rho_lb, sw_sig_t, sw_sig_ang;
@@ -59,6 +61,9 @@ struct DockArgs {
   uint32_t k0, k1;
   double cx_rate, mut_rate, tour_p, rho, eps, mut_t, mut_theta, mut_rot;
 };
+
+// ligands packed two individuals per wavefront in the local search
+constexpr int kDualAtoms = 32, kDualTor = 25;
 
 hipError_t launch_dock_init(const EvalConst &C, int cap, const DockArgs &D, hipStream_t s);
 hipError_t launch_ga_generation(const EvalConst &C, int cap, const DockArgs &D, int gen, hipStream_t s);
@@ -138,11 +143,13 @@ struct ad_ctx {
   bool use_graph = true;
   bool autotune = true;
   int forced_stage = -1;
+  bool pack_small = true;   // two small ligands' individuals per wavefront in the local search
   hipStream_t aux_stream = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   std::map<std::vector<int64_t>, int> tune_cache;
   int last_stage[2] = {-1, -1};
   int last_graph = 0;
+  int last_packed = 0;      // runs of the last dock call packed two individuals per wavefront
   uint64_t next_batch_uid = 1;
   std::string err;
 

@@ -237,12 +237,13 @@ int dock_impl(ad_ctx *c, const ad_batch *b, int n_lig, const int *sel, const ad_
   const size_t sz_lT = align256((size_t)n_lig * 3 * sizeof(float));
   const size_t sz_li = align256((size_t)n_lig * sizeof(int));
   const size_t sz_map = sel ? align256((size_t)n_lig * sizeof(int)) : 0;
+  const size_t sz_rl = align256((size_t)n_runs * sizeof(int));
   const size_t sz_act = per_run ? align256((size_t)n_runs * sizeof(unsigned int)) : 0;
   const size_t sz_lgen = per_run ? align256((size_t)n_runs * sizeof(int)) : 0;
   const size_t sz_hist = per_run ? align256((size_t)n_runs * 10 * sizeof(float)) : 0;
   const size_t sz_nact = per_run ? align256((size_t)(G + 1) * sizeof(int)) : 0;
   const size_t total = sz_geno + sz_E + sz_ev + sz_ord + sz_id + sz_bE + sz_bG + sz_lG + sz_lE + sz_lT + sz_li +
-                       sz_map + sz_act + sz_lgen + sz_hist + sz_nact;
+                       sz_map + sz_rl + sz_act + sz_lgen + sz_hist + sz_nact;
   hipSetDevice(c->device);
   if (c->dock_bytes < total) {
     hipStreamSynchronize(c->stream);
@@ -270,11 +271,13 @@ int dock_impl(ad_ctx *c, const ad_batch *b, int n_lig, const int *sel, const ad_
   float *d_lT = (float *)carve(sz_lT);
   int *d_li = (int *)carve(sz_li);
   int *d_map = sel ? (int *)carve(sz_map) : nullptr;
+  int *d_rl = (int *)carve(sz_rl);
   D.active = per_run ? (unsigned int *)carve(sz_act) : nullptr;
   D.last_gen = per_run ? (int *)carve(sz_lgen) : nullptr;
   D.hist = per_run ? (float *)carve(sz_hist) : nullptr;
   D.n_active = per_run ? (int *)carve(sz_nact) : nullptr;
   D.run_order = d_order;
+  D.n_dual = 0;
   D.lig_id = d_id;
   D.lig_map = d_map;
   D.ls_method = p->ls_method;
@@ -308,22 +311,33 @@ int dock_impl(ad_ctx *c, const ad_batch *b, int n_lig, const int *sel, const ad_
   // runs grouped by kernel atom capacity (bucket 0: <= 64 atoms, bucket 1:
   // <= 128), each bucket in longest-processing-time order so the last
   // work-groups of every launch are the cheap ones
+  // ADADELTA runs of small ligands (at most kDualAtoms atoms and kDualTor
+  // torsions) go first in bucket 0, as whole ligands: their local search
+  // packs two individuals per wavefront
+  const bool pack = c->pack_small && p->ls_method == 0 && n_ls > 0 && p->ls_iters > 0;
   std::vector<double> cost(n_lig);
-  std::vector<int> bucket_of(n_lig);
+  std::vector<int> bucket_of(n_lig), packed(n_lig);
   for (int l = 0; l < n_lig; ++l) {
     const LigDesc &d = b->lig_host[bidx(l)];
     cost[l] = d.n_pairs + 4.0 * d.n_atoms + 2.0 * d.n_tor;
     bucket_of[l] = d.n_atoms > 64 ? 1 : 0;
+    packed[l] = pack && d.n_atoms <= kDualAtoms && d.n_tor <= kDualTor;
   }
   std::vector<int> order;
   order.reserve(n_runs);
   int bstart[3] = {0, 0, n_runs};
+  int n_dual = 0;
   for (int bk = 0; bk < 2; ++bk) {
     bstart[bk] = (int)order.size();
-    for (int R = 0; R < n_runs; ++R)
-      if (bucket_of[R / p->nrun] == bk) order.push_back(R);
-    std::stable_sort(order.begin() + bstart[bk], order.end(),
-                     [&](int x, int y) { return cost[x / p->nrun] > cost[y / p->nrun]; });
+    for (int grp = 1; grp >= 0; --grp) {   // bucket 0: the packed group first
+      const size_t g0 = order.size();
+      for (int R = 0; R < n_runs; ++R)
+        if (bucket_of[R / p->nrun] == bk && packed[R / p->nrun] == grp) order.push_back(R);
+      // stable: the runs of one ligand stay consecutive
+      std::stable_sort(order.begin() + g0, order.end(),
+                       [&](int x, int y) { return cost[x / p->nrun] > cost[y / p->nrun]; });
+      if (bk == 0 && grp == 1) n_dual = (int)(order.size() - g0);
+    }
   }
   std::vector<uint32_t> ids(n_lig);
   for (int l = 0; l < n_lig; ++l) ids[l] = lig_ids ? lig_ids[l] : (uint32_t)bidx(l);
@@ -348,6 +362,7 @@ int dock_impl(ad_ctx *c, const ad_batch *b, int n_lig, const int *sel, const ad_
     Db[bk].run_order = d_order + bstart[bk];
     Db[bk].n_launch = bstart[bk + 1] - bstart[bk];
     Db[bk].stage_pairs = 0;
+    Db[bk].n_dual = bk == 0 ? n_dual : 0;
     n_buckets += Db[bk].n_launch > 0;
   }
   {
@@ -360,7 +375,7 @@ int dock_impl(ad_ctx *c, const ad_batch *b, int n_lig, const int *sel, const ad_
     c->last_stage[bk] = -1;
     if (!Db[bk].n_launch || !do_ls) continue;
     int st = 0;
-    if (p->ls_method == 1) {   // pair staging applies to the gradient local search only
+    if (p->ls_method == 1 || Db[bk].n_dual > 0) {   // no pair staging: Solis-Wets, or packed runs
       c->last_stage[bk] = 0;
       continue;
     }
@@ -391,6 +406,7 @@ int dock_impl(ad_ctx *c, const ad_batch *b, int n_lig, const int *sel, const ad_
   };
   const bool graph = c->use_graph && !c->timing && G > 0 && !per_run;
   c->last_graph = graph ? 1 : 0;
+  c->last_packed = n_dual;
   if (per_run) {
     // generations until every run has stopped: the status kernel decides
     // per run after each generation; the host looks every 16 generations
@@ -455,6 +471,15 @@ int dock_impl(ad_ctx *c, const ad_batch *b, int n_lig, const int *sel, const ad_
     if (e != hipSuccess) return c->hip_fail(e, "generation-loop graph");
   }
   HIP_TRY(c, launch_dock_finalize(D, G & 1, d_bE, d_bG, c->stream));
+  if (n_dual > 0) {
+    // the packed local search sums a pose's energy in another order (one
+    // wavefront half); report every run's best energy as the one-wavefront
+    // evaluation gives it, so that it re-scores bitwise (ad_score_poses)
+    std::vector<int> rl(n_runs);
+    for (int R = 0; R < n_runs; ++R) rl[R] = bidx(R / p->nrun);
+    HIP_TRY(c, hipMemcpyAsync(d_rl, rl.data(), n_runs * sizeof(int), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, launch_score(C, cap, n_runs, d_rl, d_bG, d_bE, nullptr, nullptr, c->stream));
+  }
 
   std::vector<float> bE(n_runs), bG((size_t)n_runs * kStride);
   std::vector<unsigned long long> ev(n_runs);
@@ -521,16 +546,18 @@ extern "C" int ad_dock_select(ad_ctx *c, const ad_batch *b, int n, const int *li
   return dock_impl(c, b, n, lig_idx, p, seed, nullptr, out, run_energy, run_genotype);
 }
 
-extern "C" int ad_set_schedule(ad_ctx *c, int use_graph, int autotune, int stage_pairs) {
+extern "C" int ad_set_schedule(ad_ctx *c, int use_graph, int autotune, int stage_pairs, int pack_small) {
   if (!c) return AD_E_INVALID;
   c->use_graph = use_graph != 0;
+  c->pack_small = pack_small != 0;
   c->autotune = autotune != 0;
   c->forced_stage = stage_pairs < 0 ? -1 : stage_pairs;
   return AD_OK;
 }
 
-extern "C" int ad_get_schedule(ad_ctx *c, int *stage_pairs, int *graph_used) {
+extern "C" int ad_get_schedule(ad_ctx *c, int *stage_pairs, int *graph_used, int *packed_runs) {
   if (!c) return AD_E_INVALID;
+  if (packed_runs) *packed_runs = c->last_packed;
   if (stage_pairs) {
     stage_pairs[0] = c->last_stage[0];
     stage_pairs[1] = c->last_stage[1];

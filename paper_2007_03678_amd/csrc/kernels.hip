@@ -65,8 +65,42 @@ __device__ __forceinline__ double wave_last(double v) {
 
 __device__ __forceinline__ double wave_sum(double v) { return wave_last(wave_incl_scan(v)); }
 
+// The same over groups of W lanes: W = 64 is the whole wavefront; W = 32
+// splits it into two halves (lanes 0-31 and 32-63) that scan and sum
+// independently (`half` = lane >> 5).
+template <int W>
+__device__ __forceinline__ double grp_incl_scan(double v) {
+  v += dpp_shr_f64<0x111>(v);    // row_shr:1
+  v += dpp_shr_f64<0x112>(v);    // row_shr:2
+  v += dpp_shr_f64<0x114>(v);    // row_shr:4
+  v += dpp_shr_f64<0x118>(v);    // row_shr:8
+  v += dpp_f64<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+  if (W == 64) v += dpp_f64<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+  return v;
+}
+
+template <int W>
+__device__ __forceinline__ double grp_last(double v, int half) {
+  if (W == 64) return wave_last(v);
+  const int l = (int)__double2loint(v), h = (int)__double2hiint(v);
+  const int lo0 = __builtin_amdgcn_readlane(l, 31), hi0 = __builtin_amdgcn_readlane(h, 31);
+  const int lo1 = __builtin_amdgcn_readlane(l, 63), hi1 = __builtin_amdgcn_readlane(h, 63);
+  return half ? __hiloint2double(hi1, lo1) : __hiloint2double(hi0, lo0);
+}
+
+template <int W>
+__device__ __forceinline__ double grp_sum(double v, int half) { return grp_last<W>(grp_incl_scan<W>(v), half); }
+
 __device__ __forceinline__ float lane_f32(float v, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+// lane k of this lane's group
+template <int W>
+__device__ __forceinline__ float grp_lane_f32(float v, int k, int half) {
+  if (W == 64) return lane_f32(v, k);
+  const float a = lane_f32(v, k), b = lane_f32(v, 32 + k);
+  return half ? b : a;
 }
 
 __device__ __forceinline__ float fast_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
@@ -199,15 +233,15 @@ __device__ __forceinline__ double wrap_angle(double th) {
 // ---------------------------------------------------------------------------
 // Shared memory of one evaluating wavefront.  CAP = atom capacity (64/128).
 // ---------------------------------------------------------------------------
-template <int CAP>
+template <int CAP, int NT = kMaxTor>
 struct EvalLds {
   double x[CAP][3];   // posed coordinates
   double g[CAP][3];   // dE/dx accumulators
   union {
-    double tm[kMaxTor][12];   // torsion rigid transforms T_k = (R_k | w_k) (pose phase)
+    double tm[NT][12];        // torsion rigid transforms T_k = (R_k | w_k) (pose phase)
     double pre[CAP][6];       // inclusive prefix sums of (g, (x-t) x g) (gradient phase)
   };
-  int tpar[kMaxTor];          // parent torsion of each torsion (-1: root fragment)
+  int tpar[NT];               // parent torsion of each torsion (-1: root fragment)
   double geno[kStride];        // genotype being evaluated
   double grad[kStride];        // output gradient
   double rot[9];               // global rotation matrix of the pose
@@ -225,8 +259,8 @@ __device__ __forceinline__ int opaque_zero() {
 }
 
 // Per-kernel set-up of the evaluation LDS (before the first barrier).
-template <int CAP>
-__device__ __forceinline__ void init_eval_lds(EvalLds<CAP> &S, int lane) {
+template <int CAP, int NT>
+__device__ __forceinline__ void init_eval_lds(EvalLds<CAP, NT> &S, int lane) {
   if (lane < kScN) S.sc[lane] = kSinCosTable[lane];
 }
 
@@ -236,7 +270,6 @@ __device__ __forceinline__ void init_eval_lds(EvalLds<CAP> &S, int lane) {
 // how many wavefronts share a SIMD).
 template <int CAP>
 struct LaneLig {
-  static constexpr int APL = CAP / 64;
   LigDesc L;
   __device__ void load(const EvalConst &C, int li, int lane) { L = C.batch.lig[li]; }
 };
@@ -354,10 +387,10 @@ struct PairStage {
   int off, n;
 };
 
-template <int CAP, bool GRAD, bool STAGE = false>
-__device__ double evaluate(const EvalConst &C, const LaneLig<CAP> &LL, EvalLds<CAP> &S, int lane, double *inter_out,
-                           double *intra_out, PairStage st = PairStage{0, 0}) {
-  constexpr int APL = CAP / 64;
+template <int CAP, bool GRAD, bool STAGE = false, int W = 64, int NT = kMaxTor>
+__device__ double evaluate(const EvalConst &C, const LaneLig<CAP> &LL, EvalLds<CAP, NT> &S, int lane, double *inter_out,
+                           double *intra_out, PairStage st = PairStage{0, 0}, int half = 0) {
+  constexpr int APL = CAP / W;
   const LigDesc &L = LL.L;
   // keep the ligand records below from being hoisted out of a caller's loop,
   // and recompute the lane's addresses per evaluation (opaque_zero)
@@ -404,7 +437,7 @@ __device__ double evaluate(const EvalConst &C, const LaneLig<CAP> &LL, EvalLds<C
   double e_inter = 0.0;
 #pragma unroll
   for (int c = 0; c < APL; ++c) {
-    const int i = c * 64 + lane;
+    const int i = c * W + lane;
     if (i < L.n_atoms) {
       const AtomGeo &ag = C.batch.geo[L.atom_off + i];
       const AtomInfo &ai = C.batch.info[L.atom_off + i];
@@ -437,11 +470,11 @@ __device__ double evaluate(const EvalConst &C, const LaneLig<CAP> &LL, EvalLds<C
   const PairRec *s_pr = reinterpret_cast<const PairRec *>(dyn_lds + st.off + C.ff.n_types * C.ff.n_types * 16);
   PairRec rec_next;
   if (lane < L.n_pairs) rec_next = (STAGE && lane < st.n) ? s_pr[lane] : pr[lane];
-  for (int p = lane; p < L.n_pairs; p += 64) {
+  for (int p = lane; p < L.n_pairs; p += W) {
     const PairRec rec = rec_next;
     // the batch's pair array ends with 64 spare records, so this prefetch
     // stays in bounds; past the ligand's list it reads a record not used
-    rec_next = (STAGE && p + 64 < st.n) ? s_pr[p + 64] : pr[p + 64];
+    rec_next = (STAGE && p + W < st.n) ? s_pr[p + W] : pr[p + W];
     const LJRec lj = STAGE ? s_lj[rec.ijt >> 16] : ljt[rec.ijt >> 16];
     const int i = rec.ijt & 0xff, j = (rec.ijt >> 8) & 0xff;
     const double dx = S.x[i][0] - S.x[j][0], dy = S.x[i][1] - S.x[j][1], dz = S.x[i][2] - S.x[j][2];
@@ -462,12 +495,12 @@ __device__ double evaluate(const EvalConst &C, const LaneLig<CAP> &LL, EvalLds<C
   // one wavefront sum unless the caller wants the two parts
   double total;
   if (inter_out || intra_out) {
-    const double inter = wave_sum(e_inter), intra = wave_sum(e_intra);
+    const double inter = grp_sum<W>(e_inter, half), intra = grp_sum<W>(e_intra, half);
     if (inter_out) *inter_out = inter;
     if (intra_out) *intra_out = intra;
     total = inter + intra;
   } else {
-    total = wave_sum(e_inter + e_intra);
+    total = grp_sum<W>(e_inter + e_intra, half);
   }
   if (!GRAD) return total;
   __syncthreads();
@@ -477,7 +510,7 @@ __device__ double evaluate(const EvalConst &C, const LaneLig<CAP> &LL, EvalLds<C
   double vv[APL][6];
 #pragma unroll
   for (int c = 0; c < APL; ++c) {
-    const int i = c * 64 + lane;
+    const int i = c * W + lane;
     if (i < L.n_atoms) {
       const double gx = S.g[i][0], gy = S.g[i][1], gz = S.g[i][2];
       const double rx = S.x[i][0] - t0, ry = S.x[i][1] - t1, rz = S.x[i][2] - t2;
@@ -493,17 +526,17 @@ __device__ double evaluate(const EvalConst &C, const LaneLig<CAP> &LL, EvalLds<C
   __syncthreads();   // tm (pose phase) is dead; pre aliases it
 #pragma unroll
   for (int c = 0; c < APL; ++c) {
-    const int i = c * 64 + lane;
+    const int i = c * W + lane;
 #pragma unroll
     for (int e = 0; e < 6; ++e) {
-      double s = wave_incl_scan(vv[c][e]) + carry[e];
+      double s = grp_incl_scan<W>(vv[c][e]) + carry[e];
       if (i < L.n_atoms) S.pre[i][e] = s;
-      carry[e] = wave_last(s);
+      carry[e] = grp_last<W>(s, half);
     }
   }
   __syncthreads();
   const int nl = L.n_atoms - 1;
-  if (lane < kStride) {
+  if (lane < kStride && lane < W) {
     double gv = 0.0;
     if (lane < 6) gv = S.pre[nl][lane];   // dE/dt and dE/domega: totals
     S.grad[lane] = gv;
@@ -578,14 +611,16 @@ __global__ __launch_bounds__(64) void k_score(EvalConst C, int n, const int *__r
 // Degrees of freedom on lanes: 0-2 translation, 3-5 rotation vector,
 // 7..7+T-1 torsions (lane 6 is the fourth quaternion slot).
 // ---------------------------------------------------------------------------
-template <int CAP, bool STAGE = false>
-__device__ void adadelta_wave(const EvalConst &C, const LaneLig<CAP> &LL, EvalLds<CAP> &S, int lane, float *geno_io,
-                              float *E_io, int iters, double rho_d, double eps_d, PairStage st = PairStage{0, 0}) {
+template <int CAP, bool STAGE = false, int W = 64, int NT = kMaxTor>
+__device__ void adadelta_wave(const EvalConst &C, const LaneLig<CAP> &LL, EvalLds<CAP, NT> &S, int lane,
+                              float *geno_io, float *E_io, int iters, double rho_d, double eps_d,
+                              PairStage st = PairStage{0, 0}, int half = 0, bool write = true) {
   const int T = LL.L.n_tor;
   // genes are FP32 values; the step arithmetic runs in FP32 with native
   // square roots (the accumulated squared gradient in FP64: gradients of
   // clashing poses overflow FP32 when squared)
-  float gene = lane < kStride ? geno_io[lane] : 0.0f;
+  const bool gl = lane < kStride && lane < W;   // the lane holds a gene slot
+  float gene = gl ? geno_io[lane] : 0.0f;
   float best_gene = gene;
   double best_E = INFINITY;
   double Eg2 = 0.0;
@@ -595,9 +630,9 @@ __device__ void adadelta_wave(const EvalConst &C, const LaneLig<CAP> &LL, EvalLd
     // step constants recomputed from the (scalar) arguments every iteration
     const double zd = (double)opaque_zero();
     const float rho = (float)(rho_d + zd), eps = (float)(eps_d + zd);
-    if (lane < kStride) S.geno[lane] = (double)gene;
+    if (gl) S.geno[lane] = (double)gene;
     __syncthreads();
-    const double E = evaluate<CAP, true, STAGE>(C, LL, S, lane, nullptr, nullptr, st);
+    const double E = evaluate<CAP, true, STAGE, W, NT>(C, LL, S, lane, nullptr, nullptr, st, half);
     const double gd = dof ? S.grad[lane] : 0.0;
     if (E < best_E) {
       best_E = E;
@@ -608,8 +643,10 @@ __device__ void adadelta_wave(const EvalConst &C, const LaneLig<CAP> &LL, EvalLd
     const float dx = dof ? -__builtin_amdgcn_sqrtf(Edx2 + eps) * rg * (float)gd : 0.0f;
     Edx2 = rho * Edx2 + (1.0f - rho) * dx * dx;
     // orientation: q <- exp(dw/2) (x) q from the three rotation lanes
-    const float w0 = lane_f32(dx, 3), w1 = lane_f32(dx, 4), w2 = lane_f32(dx, 5);
-    const float qw = lane_f32(gene, 3), qx = lane_f32(gene, 4), qy = lane_f32(gene, 5), qz = lane_f32(gene, 6);
+    const float w0 = grp_lane_f32<W>(dx, 3, half), w1 = grp_lane_f32<W>(dx, 4, half);
+    const float w2 = grp_lane_f32<W>(dx, 5, half);
+    const float qw = grp_lane_f32<W>(gene, 3, half), qx = grp_lane_f32<W>(gene, 4, half);
+    const float qy = grp_lane_f32<W>(gene, 5, half), qz = grp_lane_f32<W>(gene, 6, half);
     const float th = __builtin_amdgcn_sqrtf(w0 * w0 + w1 * w1 + w2 * w2);
     float sh, ch;
     __sincosf(0.5f * th, &sh, &ch);
@@ -632,8 +669,8 @@ __device__ void adadelta_wave(const EvalConst &C, const LaneLig<CAP> &LL, EvalLd
     }
     __syncthreads();
   }
-  if (lane < kStride) geno_io[lane] = best_gene;
-  if (lane == 0) *E_io = (float)best_E;
+  if (gl && write) geno_io[lane] = best_gene;
+  if (lane == 0 && write) *E_io = (float)best_E;
 }
 
 template <int CAP>
@@ -826,6 +863,56 @@ __global__ __launch_bounds__(64) void k_ga_generation(EvalConst C, DockArgs D, i
   }
 }
 
+// ADADELTA for small ligands (at most kDualAtoms atoms and kDualTor
+// torsions): two individuals per wavefront, one per half of 32 lanes
+// (atoms, torsions and degrees of freedom on lanes, pairs strided by 32),
+// each half with its own LDS.  The halves take individuals of one ligand:
+// the packed part of a bucket's run order holds whole ligands (nrun
+// consecutive runs each), and work-group w of a ligand takes its items 2w
+// and 2w + 1 (item = run slot * n_ls + pick).  A half without an item (odd
+// item count) or whose run has stopped computes on a valid individual and
+// writes nothing, so both halves pass the same barriers.  `wg` numbers the
+// packed work-groups; dynamic LDS: 2 * pop ints (each half's pick
+// permutation).
+__device__ void ls_dual(const EvalConst &C, const DockArgs &D, int gen, int wg, EvalLds<kDualAtoms, kDualTor> *S2) {
+  extern __shared__ __attribute__((aligned(16))) char dyn_lds[];
+  const int half = threadIdx.x >> 5, lane = threadIdx.x & 31;
+  EvalLds<kDualAtoms, kDualTor> &S = S2[half];
+  init_eval_lds(S, lane);
+  int *perm = reinterpret_cast<int *>(dyn_lds) + half * D.pop;
+  const int items = D.nrun * D.n_ls;
+  const int wpl = (items + 1) >> 1;   // work-groups per ligand
+  const int chunk = wg / wpl;
+  const int k = (wg - chunk * wpl) * 2 + half;
+  const int li = D.run_order[chunk * D.nrun] / D.nrun;   // the chunk's ligand (uniform)
+  bool live = k < items;
+  const int run_slot = live ? k / D.n_ls : 0;
+  const int slot = live ? k - run_slot * D.n_ls : 0;
+  const int R = D.run_order[chunk * D.nrun + run_slot];
+  if (D.active && !D.active[R]) live = false;
+  const int run = R % D.nrun;
+  const int m = D.pop - 1;
+  for (int j = lane; j < m; j += 32) perm[j] = j + 1;
+  __syncthreads();
+  const Rng rng{D.k0, D.k1, D.lig_id[li], (uint32_t)run, (uint32_t)gen};
+  if (lane == 0 && live) {
+    for (int s = 0; s <= slot; ++s) {
+      const int r = s + (int)randint(rng.word(0, kStLsPick, s), (uint32_t)(m - s));
+      const int t = perm[s];
+      perm[s] = perm[r];
+      perm[r] = t;
+    }
+  }
+  __syncthreads();
+  const int indiv = perm[slot];
+  LaneLig<kDualAtoms> LL;
+  LL.load(C, D.lig_map ? D.lig_map[li] : li, lane);
+  const size_t off = pop_off(D, gen & 1, R) + indiv;
+  adadelta_wave<kDualAtoms, false, 32, kDualTor>(C, LL, S, lane, D.geno + off * kStride, D.energy + off, D.ls_iters,
+                                                 D.rho, D.eps, PairStage{0, 0}, half, live);
+  if (lane == 0 && live) atomicAdd(&D.evals[R], (unsigned long long)D.ls_iters);
+}
+
 // ADADELTA on the individuals picked for generation `gen`: n_ls distinct
 // indices from 1..pop-1 by a partial Fisher-Yates shuffle (word s of the
 // pick stream draws the partner of position s).  Dynamic LDS: pop ints.
@@ -835,12 +922,22 @@ __global__ __launch_bounds__(64) void k_ga_generation(EvalConst C, DockArgs D, i
 // Dynamic LDS: pop ints (the pick permutation), then the staged records.
 template <int CAP, bool STAGE>
 __global__ __launch_bounds__(64) void k_ls_generation(EvalConst C, DockArgs D, int gen) {
-  __shared__ EvalLds<CAP> S;
+  // the 64-atom variant without staging also runs the packed work-groups
+  // (ls_dual), after the others; both share one static LDS block
+  constexpr bool kPack = CAP == 64 && !STAGE;
+  constexpr size_t kOne = sizeof(EvalLds<CAP>), kTwo = 2 * sizeof(EvalLds<kDualAtoms, kDualTor>);
+  __shared__ __attribute__((aligned(16))) char lds[kPack && kTwo > kOne ? kTwo : kOne];
+  const int n_single = (D.n_launch - D.n_dual) * D.n_ls;
+  if (kPack && (int)blockIdx.x >= n_single) {
+    ls_dual(C, D, gen, (int)blockIdx.x - n_single, reinterpret_cast<EvalLds<kDualAtoms, kDualTor> *>(lds));
+    return;
+  }
+  EvalLds<CAP> &S = *reinterpret_cast<EvalLds<CAP> *>(lds);
   init_eval_lds(S, threadIdx.x);
   extern __shared__ __attribute__((aligned(16))) char dyn_lds[];
   int *perm = reinterpret_cast<int *>(dyn_lds);
   const int lane = threadIdx.x;
-  const int R = D.run_order[blockIdx.x / D.n_ls];
+  const int R = D.run_order[D.n_dual + blockIdx.x / D.n_ls];
   if (D.active && !D.active[R]) return;
   const int slot = blockIdx.x % D.n_ls;
   const int li = R / D.nrun, run = R % D.nrun;
@@ -1276,9 +1373,42 @@ size_t ls_dynamic_lds(const EvalConst &C, const DockArgs &D) {
   return (size_t)stage_offset(D.pop) + (size_t)C.ff.n_types * C.ff.n_types * 16 + (size_t)D.stage_pairs * 16;
 }
 
-hipError_t launch_ls_generation(const EvalConst &C, int cap, const DockArgs &D, int gen, hipStream_t s) {
-  if (D.n_launch <= 0 || D.n_ls <= 0) return hipSuccess;
+hipError_t launch_ls_generation(const EvalConst &C, int cap, const DockArgs &D0, int gen, hipStream_t s) {
+  if (D0.n_launch <= 0 || D0.n_ls <= 0) return hipSuccess;
   const dim3 block(64);
+  DockArgs D = D0;
+  if (cap <= 64 && D0.ls_method == 0 && D0.n_dual > 0 && D0.stage_pairs <= 0) {
+    // packed ligands: ceil(nrun * n_ls / 2) work-groups per ligand, after the
+    // single-individual ones in the same launch when the grid allows
+    const long long max_blocks = ((1LL << 31) - 64) / 64;
+    const long long wpl = (D0.nrun * D0.n_ls + 1) / 2;
+    const long long n_chunks = D0.n_dual / D0.nrun;
+    const long long n_single = (long long)(D0.n_launch - D0.n_dual) * D0.n_ls;
+    const size_t dyn = 2 * (size_t)D0.pop * sizeof(int);
+    if (n_single + n_chunks * wpl <= max_blocks) {
+      hipLaunchKernelGGL((k_ls_generation<64, false>), dim3((unsigned)(n_single + n_chunks * wpl)), block, dyn, s, C,
+                         D0, gen);
+      return hipGetLastError();
+    }
+    DockArgs Ds = D0;
+    Ds.run_order = D0.run_order + D0.n_dual;
+    Ds.n_launch = D0.n_launch - D0.n_dual;
+    Ds.n_dual = 0;
+    hipError_t e = Ds.n_launch > 0 ? for_run_chunks(Ds, D0.n_ls, [&](const DockArgs &Dc, dim3 g) {
+      hipLaunchKernelGGL((k_ls_generation<64, false>), g, block, dyn, s, C, Dc, gen);
+    }) : hipSuccess;
+    const long long step = std::max(1LL, max_blocks / wpl);
+    for (long long c0 = 0; c0 < n_chunks && e == hipSuccess; c0 += step) {
+      DockArgs Dc = D0;   // packed work-groups only: n_launch == n_dual
+      Dc.run_order = D0.run_order + c0 * D0.nrun;
+      Dc.n_dual = Dc.n_launch = (int)(std::min(step, n_chunks - c0) * D0.nrun);
+      hipLaunchKernelGGL((k_ls_generation<64, false>), dim3((unsigned)(Dc.n_dual / D0.nrun * wpl)), block, dyn, s, C,
+                         Dc, gen);
+      e = hipGetLastError();
+    }
+    return e;
+  }
+  D.n_dual = 0;   // every run takes one wavefront per individual
   const size_t dyn = ls_dynamic_lds(C, D);
   const bool st = D.stage_pairs > 0;
   return for_run_chunks(D, D.n_ls, [&](const DockArgs &Dc, dim3 lgrid) {

@@ -189,6 +189,49 @@ def test_schedules_give_identical_results(pkg, setup):
         batch.free()
 
 
+def test_packed_local_search_follows_the_unpacked_one(pkg, setup, orc):
+    """Ligands of at most 32 atoms and 25 torsions run their ADADELTA search
+    two individuals per wavefront.  The packed evaluation only sums in
+    another order (one wavefront half), so short searches follow the
+    unpacked ones bitwise unless an FP32 rounding flips; evaluation counts
+    are identical and every returned pose re-scores exactly.  nrun * n_ls is
+    odd (5 x 3), so the last work-group of every ligand has an idle half."""
+    ctx, grid, G = setup
+    spec = [(8, 1), (16, 3), (24, 6), (32, 9), (40, 10), (30, 25), (20, 4)]
+    ligs = [synth.ligand(120 + i, n, t) for i, (n, t) in enumerate(spec)]
+    batch = ctx.ad_load_ligands(ligs)
+    OL = [orc.ligand(l) for l in ligs]
+    small = [l.n_atoms <= 32 and OL[i].n_tor <= 25 for i, l in enumerate(ligs)]
+    p = small_params(pkg, nrun=5, max_gens=4, ls_iters=30)
+    try:
+        ctx.ad_set_schedule(pack_small=True)
+        r1 = ctx.ad_dock_batch(batch, p, 9, per_run=True)
+        assert ctx.ad_get_schedule()["packed_runs"] == 5 * sum(small)
+        ctx.ad_set_schedule(pack_small=False)
+        r0 = ctx.ad_dock_batch(batch, p, 9, per_run=True)
+        assert ctx.ad_get_schedule()["packed_runs"] == 0
+        # autostop (runs stop on their own) with packing
+        ctx.ad_set_schedule(pack_small=True)
+        ra = ctx.ad_dock_batch(batch, small_params(pkg, nrun=5, max_gens=60, ls_iters=30, autostop=1), 9,
+                               per_run=True)
+    finally:
+        ctx.ad_set_schedule()
+    assert np.array_equal(r1["evals"], r0["evals"])
+    same = np.mean(r1["run_energy"] == r0["run_energy"])
+    assert same >= 0.9, same
+    assert np.array_equal(r1["run_energy"][~np.array(small)], r0["run_energy"][~np.array(small)])
+    for r in (r1, ra):
+        for l in range(len(ligs)):
+            Er, _, _ = ctx.ad_score_poses(batch, np.full(5, l, np.int32), r["run_genotype"][l])
+            assert np.array_equal(Er, r["run_energy"][l])
+            Eo, _, _ = orc.score(OL[l], G, r["best_genotype"][l].astype(np.float64))
+            assert abs(r["best_energy"][l] - Eo) <= max(E_ABS, E_REL * abs(Eo))
+    per_gen = 29 + 3 * 30
+    assert np.all(ra["evals"] >= 5 * (30 + 9 * per_gen)) and np.all(ra["evals"] <= 5 * (30 + 60 * per_gen))
+    assert np.all((ra["evals"] - 5 * 30) % per_gen == 0)
+    batch.free()
+
+
 def test_packed_loading_docks_the_same(pkg, setup):
     """Ligands loaded back to back (ad_load_ligands_packed) prepare and dock
     bitwise as the same ligands loaded one structure each."""
