@@ -158,7 +158,8 @@ def screened_campaign(args, log_fn):
     64^3 grid), then ranks the campaign set (126^3 grid over the same
     receptor); the top fraction is docked with the campaign's parameters.  A
     random holdout docked in full is the judge of recall and gives the plain
-    rate."""
+    rate; recall and the share of the ranking needed for 95 % recall are
+    also pooled over several disjoint holdouts."""
     import numpy as np
     import torch
 
@@ -212,23 +213,35 @@ def screened_campaign(args, log_fn):
     r_sel = ctx.ad_dock_select(cb, sel, p_full, seed)
     t_screened = time.perf_counter() - t0
     log_fn(f"campaign: screened step (rank {n}, dock {len(sel)}) {t_screened:.1f}s")
-    # judge: a random holdout docked in full (the plain rate and recall)
-    hold = np.sort(np.random.default_rng(seed).choice(n, size=min(args.holdout, n), replace=False)).astype(np.int32)
+    # judge: random holdouts docked in full (the plain rate and recall).  The
+    # first is the configuration's holdout; recall is also pooled over
+    # `holdout_seeds` disjoint holdouts of the same size (one docking call)
+    k_h = max(1, args.holdout_seeds)
+    size = min(args.holdout, n // k_h)
+    draw = np.random.default_rng(seed).choice(n, size=size * k_h, replace=False)
+    holds = [np.sort(draw[i * size:(i + 1) * size]).astype(np.int32) for i in range(k_h)]
+    all_h = np.concatenate(holds)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    r_hold = ctx.ad_dock_select(cb, hold, p_full, seed)
+    r_hold = ctx.ad_dock_select(cb, all_h, p_full, seed)
     t_hold = time.perf_counter() - t0
-    log_fn(f"campaign: holdout of {len(hold)} docked in {t_hold:.1f}s")
-    judge = r_hold["best_energy"].astype(np.float64)
+    log_fn(f"campaign: {k_h} holdouts of {size} docked in {t_hold:.1f}s")
+    judge_all = r_hold["best_energy"].astype(np.float64)
+    judge, hold = judge_all[:size], holds[0]
     ph = pred[hold]
     hits, pos = screen.recall(judge, screen.top_fraction(ph, args.screen_frac), top_frac=0.01)
     lo, hi = screen.clopper_pearson(hits, pos)
     f95 = screen.fraction_for_recall(ph, judge, 0.95, 0.01)
-    plain_rate = len(hold) / t_hold
+    plain_rate = len(all_h) / t_hold
     from scipy.stats import spearmanr
     rho = float(spearmanr(ph, judge)[0])
     nat = camp.n_atoms_per_ligand[hold].astype(np.float64)
     size_hits, _ = screen.recall(judge, screen.top_fraction(-nat, args.screen_frac), top_frac=0.01)
+    ph_hits = [screen.recall(judge_all[i * size:(i + 1) * size], screen.top_fraction(pred[holds[i]], args.screen_frac),
+                             top_frac=0.01) for i in range(k_h)]
+    p_hits, p_pos = sum(h for h, _ in ph_hits), sum(q for _, q in ph_hits)
+    p_lo, p_hi = screen.clopper_pearson(p_hits, p_pos)
+    f95_pool = screen.fraction_for_recall(pred[all_h], judge_all, 0.95, 0.01)
     evals_sel = int(r_sel["evals"].sum())
     out = {
         "workload": (f"campaign: {n} ligands (atoms lognormal median 32 in 10-100, torsions 0-32), 8,000-atom "
@@ -248,7 +261,10 @@ def screened_campaign(args, log_fn):
         "size_heuristic_recall": round(size_hits / pos, 4),
         "holdout_spearman": round(rho, 4),
         "frac_for_95pct_recall": round(f95, 4),
-        "screened_ligands_per_s_at_95pct_recall_derived": round(n / (t_pred + f95 * n / plain_rate), 3),
+        "pooled": {"holdouts": k_h, "ligands": int(len(all_h)), "recall_hits": [int(p_hits), int(p_pos)],
+                   "recall_top1pct": round(p_hits / p_pos, 4), "recall_ci95": [round(p_lo, 4), round(p_hi, 4)],
+                   "frac_for_95pct_recall": round(f95_pool, 4)},
+        "screened_ligands_per_s_at_95pct_recall_derived": round(n / (t_pred + f95_pool * n / plain_rate), 3),
         "screened_evals_per_s": round(evals_sel / (t_screened - t_pred), 1),
         "train": {"ligands": len(train), "epochs": args.epochs, "label_dock_s": round(t_label, 2),
                   "train_s": round(t_train, 2), "graphs_per_s": round(len(train) * args.epochs / t_train, 1),
@@ -275,7 +291,8 @@ def main():
     ap.add_argument("--label-gens", type=int, default=10)
     ap.add_argument("--epochs", type=int, default=15)
     ap.add_argument("--campaign-evals", type=int, default=100_000, help="evaluation cap per run in the campaign")
-    ap.add_argument("--holdout", type=int, default=2048)
+    ap.add_argument("--holdout", type=int, default=2048, help="campaign ligands per holdout docked in full as the judge")
+    ap.add_argument("--holdout-seeds", type=int, default=5, help="disjoint holdouts pooled for recall")
     ap.add_argument("--screen-frac", type=float, default=0.1)
     ap.add_argument("--max-evals", type=int, default=None,
                     help="override the workload's evaluation cap per run (short profiled runs)")
