@@ -395,7 +395,12 @@ class LigandPack:
         return len(self.n_atoms_per_ligand)
 
     def __getitem__(self, i) -> Ligand:
-        return self.ligands([i])[0]
+        if not -len(self) <= i < len(self):
+            raise IndexError(i)
+        return self.ligands([i % len(self)])[0]
+
+    def __iter__(self):
+        return iter(self.ligands())
 
     def ligands(self, idx=None) -> list:
         """Ligand objects (views) for the given indices (default: all)."""

@@ -197,10 +197,11 @@ def test_state_errors(pkg, ff):
     c.close()
 
 
-@pytest.mark.parametrize("cfg", ["single24", "screen64"])
+@pytest.mark.parametrize("cfg", ["single24", "screen64", "batch4096", "campaign"])
 def test_full_size_sampled_parity(ctx, orc, cfg):
-    """Paper-scale receptor and grid: GPU-built maps, oracle maps computed lazily
-    at the nodes the sampled poses touch."""
+    """Paper-scale receptor and grid (40^3 to 126^3 nodes): GPU-built maps,
+    oracle maps computed lazily at the nodes the sampled poses touch; the
+    ligands are the first 8 of each configuration's set."""
     c = synth.config(cfg, n_ligands=8)
     grid, rec = c["grid"], c["receptor"]
     ctx.ad_build_grids(grid, rec)
