@@ -287,7 +287,7 @@ def main():
     ap.add_argument("--no-campaign", action="store_true", help="skip the plain-vs-screened campaign")
     ap.add_argument("--no-batch4096", action="store_true", help="skip the batched uneven docking leg")
     ap.add_argument("--campaign-ligands", type=int, default=65536)
-    ap.add_argument("--train-ligands", type=int, default=32768)
+    ap.add_argument("--train-ligands", type=int, default=200_000)
     ap.add_argument("--label-gens", type=int, default=10)
     ap.add_argument("--epochs", type=int, default=15)
     ap.add_argument("--campaign-evals", type=int, default=100_000, help="evaluation cap per run in the campaign")
