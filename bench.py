@@ -385,7 +385,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64/f32",
         "data": "synthetic",
         "config": {
             "workload": (f"{args.workload}: {n_lig} ligands (atoms {min(i['n_atoms'] for i in infos)}-"
