@@ -25,7 +25,7 @@ ERR_NAMES = {0: "AD_OK", -1: "AD_E_INVALID", -2: "AD_E_NOMAP", -3: "AD_E_OOM", -
 MAX_TYPES, STRIDE = 16, 40
 
 EXPORTS = ["ad_create", "ad_destroy", "ad_last_error", "ad_set_stream", "ad_synchronize", "ad_load_grids",
-           "ad_build_grids", "ad_ligand_check", "ad_load_ligands", "ad_load_ligands_packed", "ad_free_batch", "ad_batch_info",
+           "ad_build_grids", "ad_ligand_check", "ad_load_ligands", "ad_load_ligands_packed", "ad_free_batch", "ad_dock_stream", "ad_batch_info",
            "ad_score_poses", "ad_dock_batch", "ad_dock_select", "ad_local_search", "ad_solis_wets", "ad_initial_population",
            "ad_set_kernel_timing", "ad_get_kernel_timing", "ad_set_schedule", "ad_get_schedule",
            "ad_prescreen_n_params", "ad_prescreen_create",
@@ -143,6 +143,8 @@ def lib():
     L.ad_ligand_check.argtypes = [C.POINTER(Ligand), C.c_int, C.c_char_p, C.c_int]
     L.ad_load_ligands.argtypes = [vp, C.c_int, C.POINTER(Ligand), C.POINTER(vp)]
     L.ad_load_ligands_packed.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp, vp, vp, C.POINTER(vp)]
+    L.ad_dock_stream.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp, vp, vp, C.c_int, C.POINTER(DockParams),
+                                 C.c_uint64, vp, C.POINTER(C.c_double)]
     L.ad_free_batch.argtypes = [vp]
     L.ad_free_batch.restype = None
     L.ad_batch_info.argtypes = [vp, C.c_int, ip, ip, ip, ip, ip]
@@ -442,14 +444,38 @@ class Context:
                                          rg.ctypes.data_as(C.POINTER(C.c_float)) if per_run else None))
         return self._results(res, n, re, rg, per_run)
 
+    def ad_dock_stream(self, pack, batch_size: int, params: DockParams, seed: int):
+        """Dock a back-to-back ligand set (synth.LigandPack layout) in batches
+        of batch_size, host preparation of the next batch overlapping the
+        docking of the current one."""
+        na = _np(pack.n_atoms_per_ligand, np.int32)
+        nb = _np(pack.n_bonds_per_ligand, np.int32)
+        ty = _np(pack.types, np.int32)
+        q = _np(pack.charges, np.float32)
+        xyz = _np(pack.xyz, np.float32).reshape(-1)
+        bd = _np(pack.bonds, np.int32).reshape(-1)
+        rot = _np(pack.rotatable, np.uint8)
+        n = len(na)
+        res = (DockResult * max(1, n))()
+        st = (C.c_double * 3)()
+        self._check(lib().ad_dock_stream(self.h, n, _ptr(na), _ptr(nb), _ptr(ty), _ptr(q), _ptr(xyz), _ptr(bd),
+                                         _ptr(rot), int(batch_size), C.byref(params), seed, res, st))
+        out = self._results(res, n, None, None, False)
+        out["stats"] = dict(prep_s=st[0], dock_s=st[1], wall_s=st[2])
+        return out
+
     @staticmethod
     def _results(res, n, re, rg, per_run):
-        out = dict(best_energy=np.array([res[i].best_energy for i in range(n)], np.float32),
-                   best_score=np.array([res[i].best_score for i in range(n)], np.float32),
-                   best_genotype=np.array([list(res[i].best_genotype) for i in range(n)], np.float32),
-                   best_run=np.array([res[i].best_run for i in range(n)], np.int32),
-                   generations=np.array([res[i].generations for i in range(n)], np.int32),
-                   evals=np.array([res[i].evals for i in range(n)], np.int64))
+        dt = np.dtype({"names": ["best_energy", "best_score", "best_genotype", "best_run", "generations", "evals"],
+                       "formats": ["<f4", "<f4", ("<f4", (STRIDE,)), "<i4", "<i4", "<i8"],
+                       "offsets": [DockResult.best_energy.offset, DockResult.best_score.offset,
+                                   DockResult.best_genotype.offset, DockResult.best_run.offset,
+                                   DockResult.generations.offset, DockResult.evals.offset],
+                       "itemsize": C.sizeof(DockResult)})
+        a = np.frombuffer(res, dtype=dt, count=n)
+        out = dict(best_energy=a["best_energy"].copy(), best_score=a["best_score"].copy(),
+                   best_genotype=a["best_genotype"].copy(), best_run=a["best_run"].copy(),
+                   generations=a["generations"].copy(), evals=a["evals"].copy())
         if per_run:
             out["run_energy"] = re
             out["run_genotype"] = rg

@@ -348,11 +348,10 @@ extern "C" int ad_ligand_check(const ad_ligand *lig, int n_types, char *msg, int
   return rc;
 }
 
-extern "C" int ad_load_ligands(ad_ctx *c, int n, const ad_ligand *ligs, ad_batch **out) {
-  if (!c || !out) return AD_E_INVALID;
+// The work of ad_load_ligands without touching the context's error state
+// (ad_dock_stream runs it on a worker thread while the context docks).
+int load_ligands_impl(ad_ctx *c, int n, const ad_ligand *ligs, uint64_t uid, ad_batch **out, std::string *err) {
   *out = nullptr;
-  if (n < 0 || (n > 0 && !ligs)) return c->fail(AD_E_INVALID, "bad ligand array");
-  if (!c->has_grid) return c->fail(AD_E_STATE, "load or build grids before ligands");
   // host preparation (validation, torsion tree, pair list, features) runs on
   // all host threads; the first failing ligand (lowest index) is reported
   std::vector<PreparedLigand> prep(n);
@@ -360,10 +359,13 @@ extern "C" int ad_load_ligands(ad_ctx *c, int n, const ad_ligand *ligs, ad_batch
   std::vector<std::string> prep_err(n);
   parallel_for(n, [&](int i) { prep_rc[i] = prepare_ligand(ligs[i], c->ff, c->type_to_map, &prep[i], &prep_err[i]); });
   for (int i = 0; i < n; ++i)
-    if (prep_rc[i]) return c->fail(prep_rc[i], "ligand " + std::to_string(i) + ": " + prep_err[i]);
+    if (prep_rc[i]) {
+      *err = "ligand " + std::to_string(i) + ": " + prep_err[i];
+      return prep_rc[i];
+    }
   ad_batch *b = new ad_batch();
   b->ctx = c;
-  b->uid = c->next_batch_uid++;
+  b->uid = uid;
   b->device = c->device;
   b->n_lig = n;
   std::vector<LigDesc> lig(n);
@@ -432,24 +434,43 @@ extern "C" int ad_load_ligands(ad_ctx *c, int n, const ad_ligand *ligs, ad_batch
             up((void **)&b->tors, tors.data(), tors.size() * sizeof(TorRec));
   if (!ok) {
     ad_free_batch(b);
-    return c->fail(AD_E_OOM, "cannot upload ligand batch");
+    *err = "cannot upload ligand batch";
+    return AD_E_OOM;
   }
   *out = b;
   return AD_OK;
 }
 
-extern "C" int ad_load_ligands_packed(ad_ctx *c, int n, const int *n_atoms, const int *n_bonds, const int *type_id,
-                                      const float *charge, const float *xyz, const int *bonds,
-                                      const unsigned char *rotatable, ad_batch **out) {
+extern "C" int ad_load_ligands(ad_ctx *c, int n, const ad_ligand *ligs, ad_batch **out) {
   if (!c || !out) return AD_E_INVALID;
   *out = nullptr;
-  if (n < 0 || (n > 0 && (!n_atoms || !n_bonds || !type_id || !charge || !xyz)))
-    return c->fail(AD_E_INVALID, "bad packed ligand arrays");
-  std::vector<ad_ligand> v(n);
+  if (n < 0 || (n > 0 && !ligs)) return c->fail(AD_E_INVALID, "bad ligand array");
+  if (!c->has_grid) return c->fail(AD_E_STATE, "load or build grids before ligands");
+  std::string err;
+  const int rc = load_ligands_impl(c, n, ligs, c->next_batch_uid++, out, &err);
+  return rc ? c->fail(rc, err) : AD_OK;
+}
+
+// Views of n ligands stored back to back (the ad_load_ligands_packed layout).
+int packed_views(int n, const int *n_atoms, const int *n_bonds, const int *type_id, const float *charge,
+                 const float *xyz, const int *bonds, const unsigned char *rotatable, std::vector<ad_ligand> *out,
+                 std::string *err) {
+  if (n < 0 || (n > 0 && (!n_atoms || !n_bonds || !type_id || !charge || !xyz))) {
+    *err = "bad packed ligand arrays";
+    return AD_E_INVALID;
+  }
+  std::vector<ad_ligand> &v = *out;
+  v.assign(n, ad_ligand{});
   size_t a = 0, bo = 0;
   for (int i = 0; i < n; ++i) {
-    if (n_atoms[i] < 1 || n_bonds[i] < 0) return c->fail(AD_E_INVALID, "ligand " + std::to_string(i) + ": bad counts");
-    if (n_bonds[i] > 0 && (!bonds || !rotatable)) return c->fail(AD_E_INVALID, "null bond arrays");
+    if (n_atoms[i] < 1 || n_bonds[i] < 0) {
+      *err = "ligand " + std::to_string(i) + ": bad counts";
+      return AD_E_INVALID;
+    }
+    if (n_bonds[i] > 0 && (!bonds || !rotatable)) {
+      *err = "null bond arrays";
+      return AD_E_INVALID;
+    }
     v[i].n_atoms = n_atoms[i];
     v[i].n_bonds = n_bonds[i];
     v[i].type_id = type_id + a;
@@ -460,6 +481,18 @@ extern "C" int ad_load_ligands_packed(ad_ctx *c, int n, const int *n_atoms, cons
     a += (size_t)n_atoms[i];
     bo += (size_t)n_bonds[i];
   }
+  return AD_OK;
+}
+
+extern "C" int ad_load_ligands_packed(ad_ctx *c, int n, const int *n_atoms, const int *n_bonds, const int *type_id,
+                                      const float *charge, const float *xyz, const int *bonds,
+                                      const unsigned char *rotatable, ad_batch **out) {
+  if (!c || !out) return AD_E_INVALID;
+  *out = nullptr;
+  std::vector<ad_ligand> v;
+  std::string err;
+  const int rc = packed_views(n, n_atoms, n_bonds, type_id, charge, xyz, bonds, rotatable, &v, &err);
+  if (rc) return c->fail(rc, err);
   return ad_load_ligands(c, n, v.data(), out);
 }
 

@@ -168,6 +168,14 @@ struct ad_ctx {
   }
 };
 
+// Ligand loading without the context's error state (api.cpp): the host
+// preparation and upload of ad_load_ligands, and the ligand views of the
+// back-to-back layout.  Errors come back in *err.
+int load_ligands_impl(ad_ctx *c, int n, const ad_ligand *ligs, uint64_t uid, ad_batch **out, std::string *err);
+int packed_views(int n, const int *n_atoms, const int *n_bonds, const int *type_id, const float *charge,
+                 const float *xyz, const int *bonds, const unsigned char *rotatable, std::vector<ad_ligand> *out,
+                 std::string *err);
+
 namespace ad {
 void fill_map_build_args(void *out, const ad_forcefield &ff, const ad_grid_desc *g, int n_rec, const float *xyz,
                          const int *type, const float *q, float *out4, float *soa);

@@ -12,6 +12,8 @@
 #include <algorithm>
 #include <cmath>
 #include <numeric>
+#include <chrono>
+#include <thread>
 #include <vector>
 
 #include "api_internal.h"
@@ -544,6 +546,71 @@ extern "C" int ad_dock_select(ad_ctx *c, const ad_batch *b, int n, const int *li
   if (!c) return AD_E_INVALID;
   if (n > 0 && !lig_idx) return c->fail(AD_E_INVALID, "null ligand index list");
   return dock_impl(c, b, n, lig_idx, p, seed, nullptr, out, run_energy, run_genotype);
+}
+
+extern "C" int ad_dock_stream(ad_ctx *c, int n, const int *n_atoms, const int *n_bonds, const int *type_id,
+                              const float *charge, const float *xyz, const int *bonds, const unsigned char *rotatable,
+                              int batch_size, const ad_dock_params *p, uint64_t seed, ad_dock_result *out,
+                              double *stats) {
+  if (!c) return AD_E_INVALID;
+  if (!c->has_grid) return c->fail(AD_E_STATE, "load or build grids before ligands");
+  if (batch_size < 1) return c->fail(AD_E_INVALID, "batch_size must be >= 1");
+  if (n > 0 && !out) return c->fail(AD_E_INVALID, "null result array");
+  int rc = check_params(c, p);
+  if (rc) return rc;
+  std::vector<ad_ligand> v;
+  std::string err;
+  rc = packed_views(n, n_atoms, n_bonds, type_id, charge, xyz, bonds, rotatable, &v, &err);
+  if (rc) return c->fail(rc, err);
+  using clk = std::chrono::steady_clock;
+  const auto t_wall = clk::now();
+  double prep_s = 0.0, dock_s = 0.0;
+  // batch k: ligands [k * batch_size, ...); its host preparation and upload
+  // run on a worker thread while batch k - 1 docks
+  auto load = [&](int k, ad_batch **b, std::string *e) -> int {
+    const auto t0 = clk::now();
+    const int lo = k * batch_size, cnt = std::min(batch_size, n - lo);
+    const int r = load_ligands_impl(c, cnt, v.data() + lo, c->next_batch_uid++, b, e);
+    prep_s += std::chrono::duration<double>(clk::now() - t0).count();
+    return r;
+  };
+  const int n_batches = (n + batch_size - 1) / batch_size;
+  ad_batch *cur = nullptr;
+  if (n_batches > 0) {
+    rc = load(0, &cur, &err);
+    if (rc) return c->fail(rc, err);
+  }
+  for (int k = 0; k < n_batches; ++k) {
+    const int lo = k * batch_size, cnt = std::min(batch_size, n - lo);
+    ad_batch *next = nullptr;
+    int rc_next = AD_OK;
+    std::string err_next;
+    std::thread worker;
+    if (k + 1 < n_batches) worker = std::thread([&]() { rc_next = load(k + 1, &next, &err_next); });
+    // random-stream id = index in the whole set: results do not depend on the batching
+    std::vector<uint32_t> ids(cnt);
+    for (int l = 0; l < cnt; ++l) ids[l] = (uint32_t)(lo + l);
+    const auto t0 = clk::now();
+    rc = dock_impl(c, cur, cnt, nullptr, p, seed, ids.data(), out + lo, nullptr, nullptr);
+    dock_s += std::chrono::duration<double>(clk::now() - t0).count();
+    if (worker.joinable()) worker.join();
+    ad_free_batch(cur);
+    cur = next;
+    if (rc) {
+      if (cur) ad_free_batch(cur);
+      return rc;
+    }
+    if (rc_next) {
+      if (cur) ad_free_batch(cur);
+      return c->fail(rc_next, "batch " + std::to_string(k + 1) + ", " + err_next);
+    }
+  }
+  if (stats) {
+    stats[0] = prep_s;
+    stats[1] = dock_s;
+    stats[2] = std::chrono::duration<double>(clk::now() - t_wall).count();
+  }
+  return AD_OK;
 }
 
 extern "C" int ad_set_schedule(ad_ctx *c, int use_graph, int autotune, int stage_pairs, int pack_small) {

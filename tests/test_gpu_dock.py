@@ -256,6 +256,34 @@ def test_packed_loading_docks_the_same(pkg, setup):
         ctx.ad_load_ligands_packed(bad)
 
 
+def test_streamed_docking_equals_one_batch(pkg, setup):
+    """ad_dock_stream docks a back-to-back set in batches, preparing the next
+    batch on a host thread while the current one docks.  Ligand i keeps
+    random-stream id i, so every ligand's result equals its result in one
+    batch, whatever the batch size; a bad ligand stops the call and is
+    named."""
+    ctx, grid, G = setup
+    pack = synth.ligand_set_fast(41, 11, atoms=(10, 90), torsions=(0, 24), packed=True)
+    p = small_params(pkg, nrun=3, max_gens=3, ls_iters=20)
+    batch = ctx.ad_load_ligands_packed(pack)
+    ref = ctx.ad_dock_batch(batch, p, 17)
+    batch.free()
+    for bs in (4, 11, 20):
+        r = ctx.ad_dock_stream(pack, bs, p, 17)
+        for k in ("best_energy", "best_genotype", "best_score", "evals", "best_run", "generations"):
+            assert np.array_equal(r[k], ref[k]), (bs, k)
+        st = r["stats"]
+        assert st["prep_s"] > 0 and st["dock_s"] > 0 and st["wall_s"] >= st["dock_s"]
+    bad = synth.pack_ligands(pack.ligands())
+    b0 = int(bad.n_bonds_per_ligand[:6].sum())
+    bad.bonds[b0] = [0, 500]          # ligand 6 (batch 1 at size 4): bond to a missing atom
+    with pytest.raises(pkg.AddockError) as e:
+        ctx.ad_dock_stream(bad, 4, p, 17)
+    assert "batch 1" in str(e.value) and "ligand 2" in str(e.value)
+    with pytest.raises(pkg.AddockError):
+        ctx.ad_dock_stream(pack, 0, p, 17)
+
+
 def test_dock_parameter_errors(pkg, setup):
     ctx, grid, G = setup
     batch = ctx.ad_load_ligands([synth.ligand(60, 10, 2)])
