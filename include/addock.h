@@ -277,15 +277,18 @@ int ad_initial_population(ad_ctx *ctx, const ad_batch *b, int lig, uint32_t lig_
  * (validation, torsion tree, pair list, pre-screen features, on up to 16
  * threads) and uploads it; each batch is freed after it docked.  This is
  * the paper's overlap of host set-up with GPU docking (Sec. 2.2, Fig. 1) for
- * sets too large to load at once.  Ligand i's random stream id is i, so
- * out[i] (caller-allocated, n entries) equals ad_dock_batch's result for the
- * same ligand at index i of one batch.  stats (optional, 3 doubles):
+ * sets too large to load at once.  Ligand i's random-stream id is id0 + i,
+ * so out[i] (caller-allocated, n entries) equals ad_dock_batch's result for
+ * the same ligand docked with that id, whatever the batching: a campaign
+ * resumed at ligand j (id0 = j), or split into shards, reproduces the
+ * uninterrupted run.  stats (optional, 3 doubles):
  * seconds of host preparation and upload, of docking, and wall time.  The
  * first failing ligand stops the call with its batch and index in the
  * message; results of earlier batches are already in out. */
 int ad_dock_stream(ad_ctx *ctx, int n, const int *n_atoms, const int *n_bonds, const int *type_id,
                    const float *charge, const float *xyz, const int *bonds, const unsigned char *rotatable,
-                   int batch_size, const ad_dock_params *p, uint64_t seed, ad_dock_result *out, double *stats);
+                   int batch_size, const ad_dock_params *p, uint64_t seed, uint32_t id0, ad_dock_result *out,
+                   double *stats);
 
 /* ---- docking schedule -------------------------------------------------------
  * Batched uneven docking (Sec. 2.2: many ligands of different sizes against

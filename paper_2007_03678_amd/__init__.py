@@ -144,7 +144,7 @@ def lib():
     L.ad_load_ligands.argtypes = [vp, C.c_int, C.POINTER(Ligand), C.POINTER(vp)]
     L.ad_load_ligands_packed.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp, vp, vp, C.POINTER(vp)]
     L.ad_dock_stream.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp, vp, vp, C.c_int, C.POINTER(DockParams),
-                                 C.c_uint64, vp, C.POINTER(C.c_double)]
+                                 C.c_uint64, C.c_uint32, vp, C.POINTER(C.c_double)]
     L.ad_free_batch.argtypes = [vp]
     L.ad_free_batch.restype = None
     L.ad_batch_info.argtypes = [vp, C.c_int, ip, ip, ip, ip, ip]
@@ -444,10 +444,10 @@ class Context:
                                          rg.ctypes.data_as(C.POINTER(C.c_float)) if per_run else None))
         return self._results(res, n, re, rg, per_run)
 
-    def ad_dock_stream(self, pack, batch_size: int, params: DockParams, seed: int):
+    def ad_dock_stream(self, pack, batch_size: int, params: DockParams, seed: int, id0: int = 0):
         """Dock a back-to-back ligand set (synth.LigandPack layout) in batches
         of batch_size, host preparation of the next batch overlapping the
-        docking of the current one."""
+        docking of the current one; ligand i uses random-stream id id0 + i."""
         na = _np(pack.n_atoms_per_ligand, np.int32)
         nb = _np(pack.n_bonds_per_ligand, np.int32)
         ty = _np(pack.types, np.int32)
@@ -459,7 +459,7 @@ class Context:
         res = (DockResult * max(1, n))()
         st = (C.c_double * 3)()
         self._check(lib().ad_dock_stream(self.h, n, _ptr(na), _ptr(nb), _ptr(ty), _ptr(q), _ptr(xyz), _ptr(bd),
-                                         _ptr(rot), int(batch_size), C.byref(params), seed, res, st))
+                                         _ptr(rot), int(batch_size), C.byref(params), seed, int(id0), res, st))
         out = self._results(res, n, None, None, False)
         out["stats"] = dict(prep_s=st[0], dock_s=st[1], wall_s=st[2])
         return out

@@ -550,8 +550,8 @@ extern "C" int ad_dock_select(ad_ctx *c, const ad_batch *b, int n, const int *li
 
 extern "C" int ad_dock_stream(ad_ctx *c, int n, const int *n_atoms, const int *n_bonds, const int *type_id,
                               const float *charge, const float *xyz, const int *bonds, const unsigned char *rotatable,
-                              int batch_size, const ad_dock_params *p, uint64_t seed, ad_dock_result *out,
-                              double *stats) {
+                              int batch_size, const ad_dock_params *p, uint64_t seed, uint32_t id0,
+                              ad_dock_result *out, double *stats) {
   if (!c) return AD_E_INVALID;
   if (!c->has_grid) return c->fail(AD_E_STATE, "load or build grids before ligands");
   if (batch_size < 1) return c->fail(AD_E_INVALID, "batch_size must be >= 1");
@@ -587,9 +587,9 @@ extern "C" int ad_dock_stream(ad_ctx *c, int n, const int *n_atoms, const int *n
     std::string err_next;
     std::thread worker;
     if (k + 1 < n_batches) worker = std::thread([&]() { rc_next = load(k + 1, &next, &err_next); });
-    // random-stream id = index in the whole set: results do not depend on the batching
+    // random-stream id = id0 + index in the set: results do not depend on the batching
     std::vector<uint32_t> ids(cnt);
-    for (int l = 0; l < cnt; ++l) ids[l] = (uint32_t)(lo + l);
+    for (int l = 0; l < cnt; ++l) ids[l] = id0 + (uint32_t)(lo + l);
     const auto t0 = clk::now();
     rc = dock_impl(c, cur, cnt, nullptr, p, seed, ids.data(), out + lo, nullptr, nullptr);
     dock_s += std::chrono::duration<double>(clk::now() - t0).count();

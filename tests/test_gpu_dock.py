@@ -259,8 +259,9 @@ def test_packed_loading_docks_the_same(pkg, setup):
 def test_streamed_docking_equals_one_batch(pkg, setup):
     """ad_dock_stream docks a back-to-back set in batches, preparing the next
     batch on a host thread while the current one docks.  Ligand i keeps
-    random-stream id i, so every ligand's result equals its result in one
-    batch, whatever the batch size; a bad ligand stops the call and is
+    random-stream id id0 + i, so every ligand's result equals its result in
+    one batch, whatever the batch size, and a run resumed at a later ligand
+    reproduces the uninterrupted one; a bad ligand stops the call and is
     named."""
     ctx, grid, G = setup
     pack = synth.ligand_set_fast(41, 11, atoms=(10, 90), torsions=(0, 24), packed=True)
@@ -274,6 +275,10 @@ def test_streamed_docking_equals_one_batch(pkg, setup):
             assert np.array_equal(r[k], ref[k]), (bs, k)
         st = r["stats"]
         assert st["prep_s"] > 0 and st["dock_s"] > 0 and st["wall_s"] >= st["dock_s"]
+    # resumed at ligand 5 (ids from 5): the same results as the uninterrupted run
+    r5 = ctx.ad_dock_stream(pack.subset(list(range(5, 11))), 4, p, 17, id0=5)
+    for k in ("best_energy", "best_genotype", "evals"):
+        assert np.array_equal(r5[k], ref[k][5:]), k
     bad = synth.pack_ligands(pack.ligands())
     b0 = int(bad.n_bonds_per_ligand[:6].sum())
     bad.bonds[b0] = [0, 500]          # ligand 6 (batch 1 at size 4): bond to a missing atom
