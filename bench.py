@@ -200,7 +200,10 @@ def screened_campaign(args, log_fn):
     t_label = time.perf_counter() - t0
     y = lab["best_energy"].astype(np.float64)
     log_fn(f"campaign: labels by plain docking in {t_label:.1f}s")
-    ps = pkg.Prescreen(ctx, seed=1, label_max=0.0)
+    # labels clipped at the quantile of the fraction to be docked: the network
+    # ranks the best labels among themselves and the rest count as equal
+    label_max = float(np.percentile(y, 100.0 * args.screen_frac))
+    ps = pkg.Prescreen(ctx, seed=1, label_max=label_max)
     t0 = time.perf_counter()
     curve = ps.ad_prescreen_train(tb, None, y, epochs=args.epochs, seed=2)
     t_train = time.perf_counter() - t0
@@ -281,6 +284,7 @@ def screened_campaign(args, log_fn):
         "screened_ligands_per_s_at_95pct_recall_derived": round(n / (t_pred + f95_pool * n / plain_rate), 3),
         "screened_evals_per_s": round(evals_sel / (t_screened - t_pred), 1),
         "train": {"ligands": len(train), "epochs": args.epochs, "label_dock_s": round(t_label, 2),
+                  "label_max": round(label_max, 3),
                   "train_s": round(t_train, 2), "graphs_per_s": round(len(train) * args.epochs / t_train, 1),
                   "loss_first_epoch": round(float(curve[0]), 4), "loss_last_epoch": round(float(curve[-1]), 4)},
     }
