@@ -67,6 +67,29 @@ def test_training_reduces_the_loss_and_ranks_held_out_ligands(pkg, setup):
     ps.close()
 
 
+def test_tail_focused_labels_find_the_best_ligands(pkg, setup):
+    """Labels clipped at their 10th percentile (the campaign's setting: the
+    network orders the best labels and the rest count as equal) find more of
+    the held-out top 2 % within the predicted top 10 % than labels clipped at
+    0 kcal/mol.  At this size (6,144 training ligands) the gain is small; at
+    the campaign's 200,000 it is large (measured by the bench)."""
+    from paper_2007_03678_amd import screen
+    ctx, ligs, batch, y = setup
+    perm = np.random.default_rng(0).permutation(len(ligs))
+    ho, tr = perm[:2048].astype(np.int32), perm[2048:].astype(np.int32)
+    found = {}
+    for name, lm in (("q10", float(np.percentile(y[tr], 10))), ("zero", 0.0)):
+        ps = pkg.Prescreen(ctx, seed=1, label_max=lm)
+        ps.ad_prescreen_train(batch, tr, y[tr], epochs=20, seed=2)
+        pred = ps.ad_prescreen_predict(batch, ho)
+        found[name] = screen.recall(y[ho], screen.top_fraction(pred, 0.1), top_frac=0.02)
+        ps.close()
+    print("top 2 % in top 10 %:", found)
+    (h_q, pos), (h_z, _) = found["q10"], found["zero"]
+    assert h_q >= 0.5 * pos          # five times random selection
+    assert h_q >= h_z                # training is bitwise reproducible, so this is a fixed comparison
+
+
 def test_training_is_reproducible(pkg, setup):
     ctx, ligs, batch, y = setup
     idx = np.arange(512, dtype=np.int32)
