@@ -121,7 +121,8 @@ int ad_synchronize(ad_ctx *ctx);
  * k_out*|x - x_clamped|^2 is added.  The library copies the maps (host or
  * device source) and keeps them resident until the next load or destroy.
  * Errors: AD_E_INVALID (dims < 2, spacing <= 0, bad map types, non-finite
- * values), AD_E_OOM. */
+ * values, nx*ny >= 2^24 or n_maps*nx*ny*nz >= 2^32: the kernels index map
+ * records in 32 bits), AD_E_OOM. */
 int ad_load_grids(ad_ctx *ctx, const ad_grid_desc *g, const float *maps, int ptrs_on_device);
 
 /* ad_build_grids: computes the maps on the GPU from receptor atoms (host

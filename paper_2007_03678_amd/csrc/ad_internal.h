@@ -98,9 +98,12 @@ struct BatchArgs {
   const PairRec *pairs;
   const TorRec *tors;
   const LJRec *lj;       // [n_types * n_types]
+  const double *trig;    // [kTrigN][2]: sin, cos of j * pi / (kTrigN / 2), j = 0..kTrigN-1
   int n_lig;
   int n_types;
 };
+
+constexpr int kTrigN = 128;   // table of torsion sin/cos at multiples of pi/64
 
 // Host-side prepared ligand (before upload).
 struct PreparedLigand {

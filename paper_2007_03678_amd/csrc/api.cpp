@@ -89,6 +89,7 @@ EvalConst ad_ctx::eval_const(const ad_batch *b) const {
   C.batch.pairs = b->pairs;
   C.batch.tors = b->tors;
   C.batch.lj = lj_dev;
+  C.batch.trig = trig_dev;
   C.batch.n_lig = b->n_lig;
   C.batch.n_types = ff.n_types;
   return C;
@@ -120,6 +121,9 @@ static int check_grid_desc(const ad_grid_desc *g, int n_types, std::string *msg)
   if (!g) return *msg = "null grid descriptor", AD_E_INVALID;
   if (g->nx < 2 || g->ny < 2 || g->nz < 2) return *msg = "grid needs >= 2 points per axis", AD_E_INVALID;
   if ((double)g->nx * g->ny * g->nz > 2.0e9) return *msg = "grid too large", AD_E_INVALID;
+  // the kernels index the map records in 32 bits (24-bit products)
+  if ((double)g->nx * g->ny >= 16777216.0 || (double)std::max(g->n_maps, 1) * g->nx * g->ny * g->nz >= 4294967296.0)
+    return *msg = "grid too large for the map indexing (nx*ny < 2^24, n_maps*nx*ny*nz < 2^32)", AD_E_INVALID;
   if (!(g->spacing > 0) || !finite_d(g->spacing)) return *msg = "spacing must be > 0", AD_E_INVALID;
   for (int d = 0; d < 3; ++d)
     if (!finite_d(g->origin[d])) return *msg = "non-finite origin", AD_E_INVALID;
@@ -167,6 +171,19 @@ extern "C" int ad_create(ad_ctx **out, int device, const ad_forcefield *ff, void
     ad_destroy(c);
     return AD_E_OOM;
   }
+  {
+    double trig[kTrigN][2];
+    for (int j = 0; j < kTrigN; ++j) {
+      const double a = j * (3.14159265358979323846 / (kTrigN / 2));
+      trig[j][0] = std::sin(a);
+      trig[j][1] = std::cos(a);
+    }
+    if (hipMalloc(&c->trig_dev, sizeof(trig)) != hipSuccess ||
+        hipMemcpy(c->trig_dev, trig, sizeof(trig), hipMemcpyHostToDevice) != hipSuccess) {
+      ad_destroy(c);
+      return AD_E_OOM;
+    }
+  }
   for (int t = 0; t < AD_MAX_TYPES; ++t) c->type_to_map[t] = -1;
   *out = c;
   return AD_OK;
@@ -179,6 +196,7 @@ extern "C" void ad_destroy(ad_ctx *c) {
   for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
   if (c->maps4) hipFree(c->maps4);
   if (c->lj_dev) hipFree(c->lj_dev);
+  if (c->trig_dev) hipFree(c->trig_dev);
   for (int s = 0; s < ad_ctx::kScratchSlots; ++s)
     if (c->scratch[s]) hipFree(c->scratch[s]);
   c->free_dock_buffers();

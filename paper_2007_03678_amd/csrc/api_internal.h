@@ -115,6 +115,7 @@ struct ad_ctx {
   ad::FFConst ffc;
   std::vector<ad::LJRec> lj_host;
   ad::LJRec *lj_dev = nullptr;
+  double *trig_dev = nullptr;   // sin, cos at multiples of pi/64 (torsion rotations)
   // resident grid
   bool has_grid = false;
   int grid_n[3] = {0, 0, 0};

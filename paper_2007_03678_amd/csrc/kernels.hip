@@ -5,7 +5,9 @@
 // Lanes map to atoms (atom i on lane i % 64, up to two per lane), to
 // torsions (lane k < 32) and to intramolecular pairs (strided).  Posed
 // coordinates and per-atom force accumulators live in LDS; pair records,
-// torsion records and the grid maps are read through L1/L2.
+// torsion records and the grid maps are read through L1/L2.  The ADADELTA
+// search of small ligands (at most 32 atoms, 25 torsions) packs two
+// individuals per wavefront, one per 32-lane half (ls_dual).
 //
 // Precision: geometry (pose, distances, grid coordinates and trilinear
 // weights), the energy accumulation and the gradient back-projection run in
@@ -105,54 +107,53 @@ __device__ __forceinline__ float grp_lane_f32(float v, int k, int half) {
 
 __device__ __forceinline__ float fast_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 
-// sin and cos of an FP64 angle.  Cody-Waite reduction by pi/2 (pi/2 split into
-// 33 + 33 + 53 significant bits, so k*C1 and k*C2 are exact for |k| < 2^20)
-// to r in [-pi/4, pi/4], then the Taylor series of sin (through r^17) and cos
-// (through r^16) in Horner form: truncation below 1e-17 on that interval.
+// sin and cos of an FP64 angle from a table at multiples of pi/64
+// (BatchArgs::trig, filled on the host).  Cody-Waite reduction x = k pi/64 +
+// r (pi/64 split into 33 + 33 + 53 significant bits, each term applied with
+// one FMA) leaves |r| <= pi/128; then sin x = s_k cos r + c_k sin r and
+// cos x = c_k cos r - s_k sin r, with the Taylor series of sin r (through
+// r^9) and cos r (through r^8): truncation below 1e-19 on that interval.
 // Arguments beyond 1e5 rad take the library routine.  The constants are read
 // from a table in LDS (`kSinCosTable`, copied by every evaluating kernel):
 // held in registers they would stay live across a local search's whole
 // iteration loop and cost occupancy.
-enum { kScTwoOverPi = 0, kScC1 = 1, kScC2 = 2, kScC3 = 3, kScSin = 4, kScCos = 12, kScN = 20 };
+enum { kSc64OverPi = 0, kScC1 = 1, kScC2 = 2, kScC3 = 3, kScSin = 4, kScCos = 8, kScN = 12 };
 __device__ const double kSinCosTable[kScN] = {
-    0.6366197723675814,      // 2/pi
-    1.5707963267341256,      // pi/2, first 33 bits
-    6.077100506303966e-11,   // next 33 bits
-    2.0222662487959506e-21,  // remainder
-    // sin: 1/17!, -1/15!, 1/13!, -1/11!, 1/9!, -1/7!, 1/5!, -1/3!
-    2.8114572543455206e-15, -7.647163731819816e-13, 1.6059043836821613e-10, -2.505210838544172e-08,
-    2.7557319223985893e-06, -0.0001984126984126984, 0.008333333333333333, -0.16666666666666666,
-    // cos: 1/16!, -1/14!, 1/12!, -1/10!, 1/8!, -1/6!, 1/4!, -1/2!
-    4.779477332387385e-14, -1.1470745597729725e-11, 2.08767569878681e-09, -2.755731922398589e-07,
-    2.48015873015873e-05, -0.001388888888888889, 0.041666666666666664, -0.5};
+    20.371832715762604,      // 64/pi
+    0.049087385210441425,    // pi/64, first 33 bits
+    1.8990939082199894e-12,  // next 33 bits
+    6.319582027487346e-23,   // remainder
+    // sin r = r + r z (-1/3! + z (1/5! + z (-1/7! + z / 9!))), z = r^2
+    -0.16666666666666666, 0.008333333333333333, -0.0001984126984126984, 2.7557319223985893e-06,
+    // cos r = 1 + z (-1/2! + z (1/4! + z (-1/6! + z / 8!)))
+    -0.5, 0.041666666666666664, -0.001388888888888889, 2.48015873015873e-05};
 
 // Arguments outside [-1e5, 1e5] (and NaN): the library routine, kept out of
 // line so that its own constants are not hoisted into callers' loops.
 __device__ __attribute__((noinline)) void sincos_f64_far(double x, double *sn, double *cs) { sincos(x, sn, cs); }
 
-__device__ __forceinline__ void sincos_f64(double x, double *sn, double *cs, const double *T) {
+__device__ __forceinline__ void sincos_f64(double x, double *sn, double *cs, const double *T, const double *trig) {
   if (!(fabs(x) <= 1.0e5)) {
     sincos_f64_far(x, sn, cs);
     return;
   }
-  const double k = rint(x * T[kScTwoOverPi]);
+  const double k = rint(x * T[kSc64OverPi]);
   double r = fma(-k, T[kScC1], x);
   r = fma(-k, T[kScC2], r);
   r = fma(-k, T[kScC3], r);
   const double z = r * r;
-  double ps = T[kScSin];
-#pragma unroll
-  for (int i = 1; i < 8; ++i) ps = fma(ps, z, T[kScSin + i]);
+  double ps = fma(T[kScSin + 3], z, T[kScSin + 2]);
+  ps = fma(ps, z, T[kScSin + 1]);
+  ps = fma(ps, z, T[kScSin]);
   const double sr = fma(ps * z, r, r);
-  double pc = T[kScCos];
-#pragma unroll
-  for (int i = 1; i < 8; ++i) pc = fma(pc, z, T[kScCos + i]);
+  double pc = fma(T[kScCos + 3], z, T[kScCos + 2]);
+  pc = fma(pc, z, T[kScCos + 1]);
+  pc = fma(pc, z, T[kScCos]);
   const double cr = fma(pc, z, 1.0);
-  const int q = ((int)k) & 3;
-  const double s0 = (q & 1) ? cr : sr;
-  const double c0 = (q & 1) ? sr : cr;
-  *sn = (q & 2) ? -s0 : s0;
-  *cs = ((q + 1) & 2) ? -c0 : c0;
+  const int j = ((int)k) & (kTrigN - 1);
+  const double sk = trig[2 * j], ck = trig[2 * j + 1];
+  *sn = fma(sk, cr, ck * sr);
+  *cs = fma(ck, cr, -(sk * sr));
 }
 
 // 1/sqrt(a) in FP64: hardware estimate refined by two Newton steps.
@@ -295,13 +296,16 @@ __device__ __forceinline__ double grid_energy(const GridArgs &G, double k_out, i
     i0[d] = ii;
     f[d] = uc[d] - (double)ii;
   }
-  const float4 *M = reinterpret_cast<const float4 *>(G.maps);
-  const size_t sx = 1, sy = (size_t)G.nx, sz = (size_t)G.nx * G.ny;
-  const size_t base = (size_t)m * sz * G.nz + (size_t)i0[2] * sz + (size_t)i0[1] * sy + (size_t)i0[0];
+  // record index in 32 bits with 24-bit products: the host keeps nx * ny
+  // below 2^24 and the whole map set below 2^32 records
+  const uint32_t sy = (uint32_t)G.nx, sz = (uint32_t)G.nx * (uint32_t)G.ny;
+  const uint32_t base = __umul24(__umul24((uint32_t)m, (uint32_t)G.nz) + (uint32_t)i0[2], sz) +
+                        __umul24((uint32_t)i0[1], sy) + (uint32_t)i0[0];
+  const float4 *M = reinterpret_cast<const float4 *>(G.maps) + base;
   double v[8];
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
-    size_t off = base + ((c & 1) ? sx : 0) + ((c & 2) ? sy : 0) + ((c & 4) ? sz : 0);
+    const uint32_t off = ((c & 1) ? 1u : 0u) + ((c & 2) ? sy : 0u) + ((c & 4) ? sz : 0u);
     const float4 r = M[off];
     v[c] = fma(aq, (double)r.z, fma(q, (double)r.y, (double)r.x));
   }
@@ -423,7 +427,7 @@ __device__ double evaluate(const EvalConst &C, const LaneLig<CAP> &LL, EvalLds<C
     const double to[3] = {tr.o[0], tr.o[1], tr.o[2]};
     const double tu[3] = {tr.u[0], tr.u[1], tr.u[2]};
     double sn, cs, Rk[9];
-    sincos_f64(S.geno[7 + lane], &sn, &cs, S.sc + opaque_zero());
+    sincos_f64(S.geno[7 + lane], &sn, &cs, S.sc + opaque_zero(), C.batch.trig);
     rot_matrix(tu, cs, sn, Rk);
 #pragma unroll
     for (int e = 0; e < 9; ++e) S.tm[lane][e] = Rk[e];
