@@ -127,8 +127,7 @@ def lib():
     except ImportError:
         pass
     if not os.path.exists(LIB_PATH):
-        raise RuntimeError(f"{LIB_PATH} is not built; run paper_2007_03678_amd.build() "
-                           "(or __graft_entry__.build()) first")
+        raise RuntimeError(f"{LIB_PATH} is not built; run paper_2007_03678_amd.build() first")
     L = C.CDLL(LIB_PATH)
     vp, ip, fp = C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_float)
     L.ad_create.argtypes = [C.POINTER(vp), C.c_int, C.POINTER(ForceField), vp]
