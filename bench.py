@@ -319,7 +319,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 (the workload would "
+        print(json.dumps({"error": "the docking path runs on one GPU; --gpus must be 1 (the workload would "
                                    "shard by ligand across GPUs, see the design notes)", "n_gpus": args.gpus}))
         sys.exit(2)
 
