@@ -173,7 +173,9 @@ def screened_campaign(args, log_fn):
     receptor); the top fraction is docked with the campaign's parameters.  A
     random holdout docked in full is the judge of recall and gives the plain
     rate; recall and the share of the ranking needed for 95 % recall are
-    also pooled over several disjoint holdouts."""
+    also pooled over several disjoint holdouts.  The ranking adds to the
+    network's rank a size prior whose weight is fitted on a validation tenth
+    of the labelled set."""
     import numpy as np
     import torch
 
@@ -200,14 +202,21 @@ def screened_campaign(args, log_fn):
     t_label = time.perf_counter() - t0
     y = lab["best_energy"].astype(np.float64)
     log_fn(f"campaign: labels by plain docking in {t_label:.1f}s")
+    # a validation split of the labelled set fits the size prior of the ranking
+    split = np.random.default_rng(seed + 3).permutation(len(train))
+    n_val = len(train) // 10
+    val, trn = np.sort(split[:n_val]).astype(np.int32), np.sort(split[n_val:]).astype(np.int32)
     # labels clipped at the quantile of the fraction to be docked: the network
     # ranks the best labels among themselves and the rest count as equal
-    label_max = float(np.percentile(y, 100.0 * args.screen_frac))
+    label_max = float(np.percentile(y[trn], 100.0 * args.screen_frac))
     ps = pkg.Prescreen(ctx, seed=1, label_max=label_max)
     t0 = time.perf_counter()
-    curve = ps.ad_prescreen_train(tb, None, y, epochs=args.epochs, seed=2)
+    curve = ps.ad_prescreen_train(tb, trn, y[trn], epochs=args.epochs, seed=2)
     t_train = time.perf_counter() - t0
     log_fn(f"campaign: pre-screen trained in {t_train:.1f}s, loss {curve[0]:.3f} -> {curve[-1]:.3f}")
+    prior_w, prior_f = screen.choose_prior_weight(ps.ad_prescreen_predict(tb, val), y[val],
+                                                  train.n_atoms_per_ligand[val], 0.95, 0.01)
+    log_fn(f"campaign: size prior weight {prior_w} (validation share for 95% recall {prior_f:.3f})")
     tb.free()
     # -- campaign set --------------------------------------------------------
     t0 = time.time()
@@ -225,8 +234,9 @@ def screened_campaign(args, log_fn):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     pred = ps.ad_prescreen_predict(cb)
+    rank = screen.prior_score(pred, camp.n_atoms_per_ligand, prior_w)
     t_pred = time.perf_counter() - t0
-    sel = screen.top_fraction(pred, args.screen_frac).astype(np.int32)
+    sel = screen.top_fraction(rank, args.screen_frac).astype(np.int32)
     r_sel = ctx.ad_dock_select(cb, sel, p_full, seed)
     t_screened = time.perf_counter() - t0
     log_fn(f"campaign: screened step (rank {n}, dock {len(sel)}) {t_screened:.1f}s")
@@ -245,25 +255,32 @@ def screened_campaign(args, log_fn):
     log_fn(f"campaign: {k_h} holdouts of {size} docked in {t_hold:.1f}s")
     judge_all = r_hold["best_energy"].astype(np.float64)
     judge, hold = judge_all[:size], holds[0]
-    ph = pred[hold]
+    # the screen's ranking of a subset: the prior ranks within the subset
+    def sub_rank(idx):
+        return screen.prior_score(pred[idx], camp.n_atoms_per_ligand[idx], prior_w)
+    ph = sub_rank(hold)
     hits, pos = screen.recall(judge, screen.top_fraction(ph, args.screen_frac), top_frac=0.01)
     lo, hi = screen.clopper_pearson(hits, pos)
     f95 = screen.fraction_for_recall(ph, judge, 0.95, 0.01)
     plain_rate = len(all_h) / t_hold
     from scipy.stats import spearmanr
-    rho = float(spearmanr(ph, judge)[0])
+    rho = float(spearmanr(pred[hold], judge)[0])
     nat = camp.n_atoms_per_ligand[hold].astype(np.float64)
     size_hits, _ = screen.recall(judge, screen.top_fraction(-nat, args.screen_frac), top_frac=0.01)
-    ph_hits = [screen.recall(judge_all[i * size:(i + 1) * size], screen.top_fraction(pred[holds[i]], args.screen_frac),
-                             top_frac=0.01) for i in range(k_h)]
-    p_hits, p_pos = sum(h for h, _ in ph_hits), sum(q for _, q in ph_hits)
+    def pooled(score_of):
+        hp = [screen.recall(judge_all[i * size:(i + 1) * size], screen.top_fraction(score_of(holds[i]), args.screen_frac),
+                            top_frac=0.01) for i in range(k_h)]
+        return sum(h for h, _ in hp), sum(q for _, q in hp)
+    p_hits, p_pos = pooled(sub_rank)
     p_lo, p_hi = screen.clopper_pearson(p_hits, p_pos)
-    f95_pool = screen.fraction_for_recall(pred[all_h], judge_all, 0.95, 0.01)
+    f95_pool = screen.fraction_for_recall(sub_rank(all_h), judge_all, 0.95, 0.01)
+    n_hits, _ = pooled(lambda idx: pred[idx])
+    f95_net = screen.fraction_for_recall(pred[all_h], judge_all, 0.95, 0.01)
     evals_sel = int(r_sel["evals"].sum())
     out = {
         "workload": (f"campaign: {n} ligands (atoms lognormal median 32 in 10-100, torsions 0-32), 8,000-atom "
                      f"receptor, 126^3 x 10 FP32 maps, 20 runs x pop 150, cap {args.campaign_evals} evals/run; "
-                     f"pre-screen trained on {len(train)} ligands labelled by plain docking (5 runs x pop 100, "
+                     f"pre-screen trained on {len(trn)} of {len(train)} ligands labelled by plain docking (5 runs x pop 100, "
                      f"{args.label_gens} generations, 64^3 grid)"),
         "plain_ligands_per_s": round(plain_rate, 3),
         "screened_ligands_per_s": round(n / t_screened, 3),
@@ -280,12 +297,16 @@ def screened_campaign(args, log_fn):
         "frac_for_95pct_recall": round(f95, 4),
         "pooled": {"holdouts": k_h, "ligands": int(len(all_h)), "recall_hits": [int(p_hits), int(p_pos)],
                    "recall_top1pct": round(p_hits / p_pos, 4), "recall_ci95": [round(p_lo, 4), round(p_hi, 4)],
-                   "frac_for_95pct_recall": round(f95_pool, 4)},
+                   "frac_for_95pct_recall": round(f95_pool, 4),
+                   "network_alone": {"recall_hits": [int(n_hits), int(p_pos)],
+                                     "frac_for_95pct_recall": round(f95_net, 4)}},
+        "ranking": {"size_prior_weight": prior_w, "validation_frac_for_95pct_recall": round(prior_f, 4),
+                    "validation_ligands": int(n_val)},
         "screened_ligands_per_s_at_95pct_recall_derived": round(n / (t_pred + f95_pool * n / plain_rate), 3),
         "screened_evals_per_s": round(evals_sel / (t_screened - t_pred), 1),
-        "train": {"ligands": len(train), "epochs": args.epochs, "label_dock_s": round(t_label, 2),
-                  "label_max": round(label_max, 3),
-                  "train_s": round(t_train, 2), "graphs_per_s": round(len(train) * args.epochs / t_train, 1),
+        "train": {"ligands": int(len(trn)), "labelled": len(train), "epochs": args.epochs,
+                  "label_dock_s": round(t_label, 2), "label_max": round(label_max, 3),
+                  "train_s": round(t_train, 2), "graphs_per_s": round(len(trn) * args.epochs / t_train, 1),
                   "loss_first_epoch": round(float(curve[0]), 4), "loss_last_epoch": round(float(curve[-1]), 4)},
     }
     ps.close()

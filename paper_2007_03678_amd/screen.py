@@ -45,3 +45,26 @@ def fraction_for_recall(pred_scores, judge_scores, target: float = 0.95, top_fra
     pos = np.sort(rank[top_fraction(judge_scores, top_frac)])
     need = int(math.ceil(target * len(pos) - 1e-9))
     return float(pos[need - 1] + 1) / len(pred)
+
+
+def prior_score(pred_scores, n_atoms, weight: float) -> np.ndarray:
+    """Ranking score of the screen (lower = better): the pre-screen's rank
+    plus `weight` times the rank by ligand size, larger ligands first."""
+    from scipy.stats import rankdata
+    pred = np.asarray(pred_scores, dtype=np.float64)
+    if weight == 0:
+        return rankdata(pred)
+    return rankdata(pred) + weight * rankdata(-np.asarray(n_atoms, dtype=np.float64))
+
+
+def choose_prior_weight(pred_scores, labels, n_atoms, target: float = 0.95, top_frac: float = 0.01,
+                        weights=(0.0, 0.25, 0.5, 0.75, 1.0, 1.5, 2.0)):
+    """(weight, share): the size-prior weight whose ranking of a validation
+    set needs the smallest share of the list for `target` recall of the
+    labels' top `top_frac` (the smaller weight on ties)."""
+    best = None
+    for w in weights:
+        f = fraction_for_recall(prior_score(pred_scores, n_atoms, w), labels, target, top_frac)
+        if best is None or f < best[1] - 1e-12:
+            best = (float(w), f)
+    return best

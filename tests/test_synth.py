@@ -120,3 +120,22 @@ def test_screen_helpers():
     lo, hi = screen.clopper_pearson(19, 20)
     assert lo == pytest.approx(0.7513, abs=1e-3) and hi == pytest.approx(0.9987, abs=1e-3)
     assert screen.clopper_pearson(0, 10)[0] == 0.0 and screen.clopper_pearson(10, 10)[1] == 1.0
+
+
+def test_size_prior_helpers():
+    from scipy.stats import rankdata
+    from paper_2007_03678_amd import screen
+    rng = np.random.default_rng(3)
+    n = 400
+    nat = rng.integers(10, 100, n).astype(float)
+    pred = rng.normal(size=n)
+    assert np.array_equal(screen.prior_score(pred, nat, 0.0), rankdata(pred))
+    s = screen.prior_score(pred, nat, 1.0)
+    assert np.array_equal(s, rankdata(pred) + rankdata(-nat))
+    # labels that reward size beyond what the prediction knows: a positive weight wins
+    labels = -nat + 5.0 * rng.normal(size=n)
+    w, f = screen.choose_prior_weight(pred, labels, nat, top_frac=0.05)
+    assert w > 0 and f <= screen.fraction_for_recall(pred, labels, 0.95, 0.05)
+    # a perfect prediction needs no prior
+    w0, f0 = screen.choose_prior_weight(labels, labels, nat, top_frac=0.05)
+    assert w0 == 0.0 and f0 == pytest.approx(19 / 400)   # 19 of the 20 positives first
