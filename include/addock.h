@@ -277,7 +277,7 @@ int ad_initial_population(ad_ctx *ctx, const ad_batch *b, int lig, uint32_t lig_
  * buffering: while batch k docks, a host thread prepares batch k + 1
  * (validation, torsion tree, pair list, pre-screen features, on up to 16
  * threads) and uploads it; each batch is freed after it docked.  This is
- * the paper's overlap of host set-up with GPU docking (Sec. 2.2, Fig. 1) for
+ * the paper's overlap of host set-up with GPU docking (Sec. 2.2.2, Fig. 1) for
  * sets too large to load at once.  Ligand i's random-stream id is id0 + i,
  * so out[i] (caller-allocated, n entries) equals ad_dock_batch's result for
  * the same ligand docked with that id, whatever the batching: a campaign
