@@ -236,7 +236,7 @@ __device__ __forceinline__ double wrap_angle(double th) {
 // ---------------------------------------------------------------------------
 template <int CAP, int NT = kMaxTor>
 struct EvalLds {
-  double x[CAP][3];   // posed coordinates
+  double x[3][CAP];   // posed coordinates (component-major)
   double g[CAP][3];   // dE/dx accumulators
   union {
     double tm[NT][12];        // torsion rigid transforms T_k = (R_k | w_k) (pose phase)
@@ -363,7 +363,9 @@ __device__ __forceinline__ float pair_energy(const FFConst &K, const LJRec &lj, 
   const float gds = fast_exp2(-K.ds_log2e * r2c);
   const float e_ds = dsv * gds;
   const float d_ds = -e_ds * r * K.inv_s2;
-  *fscale = floored ? 0.0f : (d_lj + d_el + d_ds) * inv_r;
+  // a select on the factor, not on the whole force, keeps the force terms
+  // out of a branch
+  *fscale = (d_lj + d_el + d_ds) * (floored ? 0.0f : inv_r);
   return e_lj + e_el + e_ds;
 }
 
@@ -460,7 +462,7 @@ __device__ double evaluate(const EvalConst &C, const LaneLig<CAP> &LL, EvalLds<C
       x[0] += t0; x[1] += t1; x[2] += t2;
       double g[3];
       e_inter += grid_energy(C.grid, C.ff.k_out, ai.map, ai.q, x, g);
-      S.x[i][0] = x[0]; S.x[i][1] = x[1]; S.x[i][2] = x[2];
+      S.x[0][i] = x[0]; S.x[1][i] = x[1]; S.x[2][i] = x[2];
       if (GRAD) { S.g[i][0] = g[0]; S.g[i][1] = g[1]; S.g[i][2] = g[2]; }
     }
   }
@@ -481,7 +483,7 @@ __device__ double evaluate(const EvalConst &C, const LaneLig<CAP> &LL, EvalLds<C
     rec_next = (STAGE && p + W < st.n) ? s_pr[p + W] : pr[p + W];
     const LJRec lj = STAGE ? s_lj[rec.ijt >> 16] : ljt[rec.ijt >> 16];
     const int i = rec.ijt & 0xff, j = (rec.ijt >> 8) & 0xff;
-    const double dx = S.x[i][0] - S.x[j][0], dy = S.x[i][1] - S.x[j][1], dz = S.x[i][2] - S.x[j][2];
+    const double dx = S.x[0][i] - S.x[0][j], dy = S.x[1][i] - S.x[1][j], dz = S.x[2][i] - S.x[2][j];
     const float r2 = (float)(dx * dx + dy * dy + dz * dz);
     float fs;
     e_intra += (double)pair_energy(C.ff, lj, rec.qq, rec.dsv, r2, &fs);
@@ -517,7 +519,7 @@ __device__ double evaluate(const EvalConst &C, const LaneLig<CAP> &LL, EvalLds<C
     const int i = c * W + lane;
     if (i < L.n_atoms) {
       const double gx = S.g[i][0], gy = S.g[i][1], gz = S.g[i][2];
-      const double rx = S.x[i][0] - t0, ry = S.x[i][1] - t1, rz = S.x[i][2] - t2;
+      const double rx = S.x[0][i] - t0, ry = S.x[1][i] - t1, rz = S.x[2][i] - t2;
       vv[c][0] = gx; vv[c][1] = gy; vv[c][2] = gz;
       vv[c][3] = ry * gz - rz * gy;
       vv[c][4] = rz * gx - rx * gz;
@@ -552,14 +554,14 @@ __device__ double evaluate(const EvalConst &C, const LaneLig<CAP> &LL, EvalLds<C
     double F[6];
 #pragma unroll
     for (int e = 0; e < 6; ++e) F[e] = S.pre[te - 1][e] - (ts > 0 ? S.pre[ts - 1][e] : 0.0);
-    const double ax = S.x[ta][0] - t0, ay = S.x[ta][1] - t1, az = S.x[ta][2] - t2;
+    const double ax = S.x[0][ta] - t0, ay = S.x[1][ta] - t1, az = S.x[2][ta] - t2;
     // torque about the axis point a: sum (x_i - t) x g_i - (x_a - t) x sum g_i
     const double tx = F[3] - (ay * F[2] - az * F[1]);
     const double ty = F[4] - (az * F[0] - ax * F[2]);
     const double tz = F[5] - (ax * F[1] - ay * F[0]);
-    const double ux = (S.x[tb][0] - S.x[ta][0]) * tinv_len;
-    const double uy = (S.x[tb][1] - S.x[ta][1]) * tinv_len;
-    const double uz = (S.x[tb][2] - S.x[ta][2]) * tinv_len;
+    const double ux = (S.x[0][tb] - S.x[0][ta]) * tinv_len;
+    const double uy = (S.x[1][tb] - S.x[1][ta]) * tinv_len;
+    const double uz = (S.x[2][tb] - S.x[2][ta]) * tinv_len;
     S.grad[7 + lane] = ux * tx + uy * ty + uz * tz;
   }
   __syncthreads();

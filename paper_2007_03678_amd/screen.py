@@ -47,14 +47,28 @@ def fraction_for_recall(pred_scores, judge_scores, target: float = 0.95, top_fra
     return float(pos[need - 1] + 1) / len(pred)
 
 
+def average_rank(values) -> np.ndarray:
+    """Ranks 1..n of `values` in ascending order, tied values sharing the
+    mean of the ranks they span."""
+    v = np.asarray(values, dtype=np.float64)
+    order = np.argsort(v, kind="stable")
+    sv = v[order]
+    first = np.concatenate(([True], sv[1:] != sv[:-1]))
+    group = np.cumsum(first) - 1                       # tie group of each sorted value
+    start = np.flatnonzero(first)                      # first sorted position of each group
+    end = np.concatenate((start[1:], [len(sv)]))       # one past its last
+    out = np.empty(len(v), dtype=np.float64)
+    out[order] = 0.5 * (start[group] + end[group] + 1)
+    return out
+
+
 def prior_score(pred_scores, n_atoms, weight: float) -> np.ndarray:
     """Ranking score of the screen (lower = better): the pre-screen's rank
     plus `weight` times the rank by ligand size, larger ligands first."""
-    from scipy.stats import rankdata
-    pred = np.asarray(pred_scores, dtype=np.float64)
+    r = average_rank(pred_scores)
     if weight == 0:
-        return rankdata(pred)
-    return rankdata(pred) + weight * rankdata(-np.asarray(n_atoms, dtype=np.float64))
+        return r
+    return r + weight * average_rank(-np.asarray(n_atoms, dtype=np.float64))
 
 
 def choose_prior_weight(pred_scores, labels, n_atoms, target: float = 0.95, top_frac: float = 0.01,

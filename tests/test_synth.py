@@ -132,6 +132,10 @@ def test_size_prior_helpers():
     assert np.array_equal(screen.prior_score(pred, nat, 0.0), rankdata(pred))
     s = screen.prior_score(pred, nat, 1.0)
     assert np.array_equal(s, rankdata(pred) + rankdata(-nat))
+    # ties share the mean of their ranks
+    assert screen.average_rank([3.0, 1.0, 3.0, 2.0, 3.0]).tolist() == [4.0, 1.0, 4.0, 2.0, 4.0]
+    heavy = rng.integers(0, 5, 1000).astype(float)
+    assert np.array_equal(screen.average_rank(heavy), rankdata(heavy))
     # labels that reward size beyond what the prediction knows: a positive weight wins
     labels = -nat + 5.0 * rng.normal(size=n)
     w, f = screen.choose_prior_weight(pred, labels, nat, top_frac=0.05)
