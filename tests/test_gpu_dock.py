@@ -332,3 +332,46 @@ def test_docking_statistics_match_oracle(pkg, ff, orc):
     assert abs(np.median(eg) - np.median(eo)) < 0.3 + 0.05 * abs(np.median(eo)), (np.median(eg), np.median(eo))
     batch.free()
     ctx.close()
+
+
+@pytest.mark.parametrize("cfg,max_evals", [("screen64", 20_000), ("batch4096", 3_000)])
+def test_full_size_docking_rescores_at_sampled_ligands(pkg, ff, orc, cfg, max_evals):
+    """A configuration's whole ligand set, receptor and grid, docked in the
+    launch configuration the benchmark times (runs, population, local search,
+    atom-capacity buckets, two-per-wavefront packing; only the evaluation cap
+    is lower).  Every returned run energy re-scores bitwise through the score
+    kernel, and the best poses of ligands sampled across the size range (packed,
+    64-atom and 128-atom buckets) re-score with the oracle's energy."""
+    c = synth.config(cfg)
+    ligs = c["ligands"]
+    ctx = pkg.create(ff, 0)
+    try:
+        ctx.ad_build_grids(c["grid"], c["receptor"])
+        batch = ctx.ad_load_ligands(ligs)
+        d = dict(c["dock"])
+        d["max_evals"] = max_evals
+        p = pkg.make_params(**d)
+        print(f"docking {cfg}: {len(ligs)} ligands, cap {max_evals} evaluations per run", flush=True)
+        r = ctx.ad_dock_batch(batch, p, c["seed"], per_run=True)
+        assert ctx.ad_get_schedule()["packed_runs"] > 0
+        n, nrun = r["run_energy"].shape
+        assert n == len(ligs) and np.all(np.isfinite(r["run_energy"]))
+        idx = np.repeat(np.arange(n, dtype=np.int32), nrun)
+        Er, _, _ = ctx.ad_score_poses(batch, idx, r["run_genotype"].reshape(n * nrun, -1))
+        assert np.array_equal(Er, r["run_energy"].reshape(-1))
+        assert np.array_equal(r["best_energy"], r["run_energy"].min(axis=1))
+        # sampled ligands: smallest, largest, and every eighth of the size order
+        nat = np.asarray(ligs.n_atoms_per_ligand) if hasattr(ligs, "n_atoms_per_ligand") else np.array([l.n_atoms for l in ligs])
+        order = np.argsort(nat, kind="stable")
+        pick = sorted(set(order[np.linspace(0, n - 1, 9).round().astype(int)].tolist()))
+        if cfg == "batch4096":
+            assert nat[pick].max() > 64   # the 128-atom bucket is sampled
+        assert nat[pick].min() <= 32      # so is a packed ligand
+        G = orc.grid(c["grid"], c["receptor"], lazy=True)
+        for i in pick:
+            Eo, _, To = orc.score(orc.ligand(ligs[i]), G, r["best_genotype"][i].astype(np.float64))
+            assert abs(r["best_energy"][i] - Eo) <= max(E_ABS, E_REL * abs(Eo)), (i, nat[i])
+            assert abs(r["best_score"][i] - To[2]) <= max(E_ABS, E_REL * abs(To[2])), (i, nat[i])
+        batch.free()
+    finally:
+        ctx.close()
