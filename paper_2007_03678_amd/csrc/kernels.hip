@@ -265,14 +265,45 @@ __device__ __forceinline__ void init_eval_lds(EvalLds<CAP, NT> &S, int lane) {
   if (lane < kScN) S.sc[lane] = kSinCosTable[lane];
 }
 
-// Ligand being evaluated.  Per-atom and per-torsion records are re-read from
-// L1-resident global memory inside every evaluation instead of being held in
-// registers across a local search's iterations (register pressure decides
-// how many wavefronts share a SIMD).
+// Ligand being evaluated, with the lane's atom records (reference
+// coordinates, map, charge, owner torsion; atom c * W + lane) and its
+// torsion's indices for the gradient phase held in registers for a whole
+// local search.  The torsion axis records of the pose phase and the pair
+// records are re-read from L1-resident global memory inside every evaluation:
+// holding those as well takes the kernel past 128 VGPRs, one wavefront per
+// SIMD fewer.
 template <int CAP>
 struct LaneLig {
+  static constexpr int kAPL = CAP >= 64 ? CAP / 64 : 1;
   LigDesc L;
-  __device__ void load(const EvalConst &C, int li, int lane) { L = C.batch.lig[li]; }
+  double y[kAPL][3];
+  int map[kAPL], owner[kAPL];
+  float q[kAPL];
+  int ts, te, ta, tb;
+  double tinv;
+  __device__ void load(const EvalConst &C, int li, int lane) {
+    L = C.batch.lig[li];
+    constexpr int W = CAP >= 64 ? 64 : 32;
+#pragma unroll
+    for (int c = 0; c < kAPL; ++c) {
+      const int i = c * W + lane;
+      if (i < L.n_atoms) {
+        const AtomGeo &ag = C.batch.geo[L.atom_off + i];
+        const AtomInfo &ai = C.batch.info[L.atom_off + i];
+        y[c][0] = ag.y[0]; y[c][1] = ag.y[1]; y[c][2] = ag.y[2];
+        map[c] = ai.map; q[c] = ai.q; owner[c] = ai.owner;
+      } else {
+        y[c][0] = y[c][1] = y[c][2] = 0.0;
+        map[c] = 0; q[c] = 0.0f; owner[c] = -1;
+      }
+    }
+    if (lane < L.n_tor) {
+      const TorRec &tr = C.batch.tors[L.tor_off + lane];
+      ts = tr.s; te = tr.e; ta = tr.a; tb = tr.b; tinv = tr.inv_len;
+    } else {
+      ts = te = ta = tb = 0; tinv = 0.0;
+    }
+  }
 };
 
 // Trilinear interpolation of map_m + q map_e + |q| map_d with its gradient,
@@ -397,6 +428,7 @@ template <int CAP, bool GRAD, bool STAGE = false, int W = 64, int NT = kMaxTor>
 __device__ double evaluate(const EvalConst &C, const LaneLig<CAP> &LL, EvalLds<CAP, NT> &S, int lane, double *inter_out,
                            double *intra_out, PairStage st = PairStage{0, 0}, int half = 0) {
   constexpr int APL = CAP / W;
+  static_assert(LaneLig<CAP>::kAPL == APL && (CAP >= 64) == (W == 64), "LaneLig holds atom c * W + lane");
   const LigDesc &L = LL.L;
   // keep the ligand records below from being hoisted out of a caller's loop,
   // and recompute the lane's addresses per evaluation (opaque_zero)
@@ -445,11 +477,9 @@ __device__ double evaluate(const EvalConst &C, const LaneLig<CAP> &LL, EvalLds<C
   for (int c = 0; c < APL; ++c) {
     const int i = c * W + lane;
     if (i < L.n_atoms) {
-      const AtomGeo &ag = C.batch.geo[L.atom_off + i];
-      const AtomInfo &ai = C.batch.info[L.atom_off + i];
       // torsions moving the atom, deepest first, then the global transform
-      double y0 = ag.y[0], y1 = ag.y[1], y2 = ag.y[2];
-      for (int k = ai.owner; k >= 0; k = S.tpar[k]) {
+      double y0 = LL.y[c][0], y1 = LL.y[c][1], y2 = LL.y[c][2];
+      for (int k = LL.owner[c]; k >= 0; k = S.tpar[k]) {
         const double *M = S.tm[k];
         const double n0 = fma(M[0], y0, fma(M[1], y1, fma(M[2], y2, M[9])));
         const double n1 = fma(M[3], y0, fma(M[4], y1, fma(M[5], y2, M[10])));
@@ -461,7 +491,7 @@ __device__ double evaluate(const EvalConst &C, const LaneLig<CAP> &LL, EvalLds<C
       for (int r = 0; r < 3; ++r) x[r] = S.rot[3 * r] * y0 + S.rot[3 * r + 1] * y1 + S.rot[3 * r + 2] * y2;
       x[0] += t0; x[1] += t1; x[2] += t2;
       double g[3];
-      e_inter += grid_energy(C.grid, C.ff.k_out, ai.map, ai.q, x, g);
+      e_inter += grid_energy(C.grid, C.ff.k_out, LL.map[c], LL.q[c], x, g);
       S.x[0][i] = x[0]; S.x[1][i] = x[1]; S.x[2][i] = x[2];
       if (GRAD) { S.g[i][0] = g[0]; S.g[i][1] = g[1]; S.g[i][2] = g[2]; }
     }
@@ -548,9 +578,8 @@ __device__ double evaluate(const EvalConst &C, const LaneLig<CAP> &LL, EvalLds<C
     S.grad[lane] = gv;
   }
   if (lane < L.n_tor) {
-    const TorRec &tr = C.batch.tors[L.tor_off + lane];
-    const int ts = tr.s, te = tr.e, ta = tr.a, tb = tr.b;
-    const double tinv_len = tr.inv_len;
+    const int ts = LL.ts, te = LL.te, ta = LL.ta, tb = LL.tb;
+    const double tinv_len = LL.tinv;
     double F[6];
 #pragma unroll
     for (int e = 0; e < 6; ++e) F[e] = S.pre[te - 1][e] - (ts > 0 ? S.pre[ts - 1][e] : 0.0);
