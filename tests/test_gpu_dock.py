@@ -96,6 +96,22 @@ def test_local_search_first_iterations_follow_oracle(pkg, setup, orc):
     batch.free()
 
 
+def chain_ligand(n, n_rot):
+    """Zigzag carbon chain (1.5 A bonds, 109.5 degree angles) whose bonds 1 ..
+    n_rot are rotatable; alternating charges summing to zero."""
+    half = np.deg2rad(109.5) / 2
+    x = np.zeros((n, 3))
+    for i in range(1, n):
+        x[i] = x[i - 1] + 1.5 * np.array([np.sin(half), np.cos(half) * (1 if i % 2 else -1), 0.0])
+    x -= x.mean(0)
+    q = np.where(np.arange(n) % 2 == 0, 0.1, -0.1)
+    q -= q.mean()
+    rot = np.zeros(n - 1, np.uint8)
+    rot[1:1 + n_rot] = 1
+    return synth.Ligand(np.full(n, synth.TYPE_ID["C"], np.int32), q.astype(np.float32), x.astype(np.float32),
+                        np.array([[i, i + 1] for i in range(n - 1)], np.int32), rot)
+
+
 def small_params(pkg, **kw):
     d = dict(nrun=4, pop=30, max_gens=8, ls_rate=0.1, ls_iters=40)
     d.update(kw)
@@ -375,3 +391,38 @@ def test_full_size_docking_rescores_at_sampled_ligands(pkg, ff, orc, cfg, max_ev
         batch.free()
     finally:
         ctx.close()
+
+
+def test_docking_extreme_ligands_and_degenerate_settings(pkg, setup, orc):
+    """Ligands at the ends of every size limit (one atom, two atoms, the
+    packing limits of 32 atoms / 25 torsions and one atom past them, 64 and 65
+    atoms, the 128-atom maximum with 32 torsions) docked with degenerate
+    search settings: a single run with a population of two and one local
+    search per generation (an idle packed half), local searches of zero
+    iterations, and a cap below one population (initial population only)."""
+    ctx, grid, G = setup
+    # random trees of 32 atoms have about 20 eligible torsions: zigzag chains
+    # reach the torsion limit of packing (25) and pass it (26)
+    spec = [(1, 0), (2, 0), (32, 25), (32, 26), (33, 20), (64, 32), (65, 32), (128, 32)]
+    ligs = [chain_ligand(n, t) if n == 32 else synth.ligand(140 + i, n, t) for i, (n, t) in enumerate(spec)]
+    batch = ctx.ad_load_ligands(ligs)
+    OL = [orc.ligand(l) for l in ligs]
+    assert [L.n_tor for L in OL[2:4]] == [25, 26]
+    packable = sum(l.n_atoms <= 32 and L.n_tor <= 25 for l, L in zip(ligs, OL))
+    cases = [(dict(nrun=1, pop=2, ls_rate=0.5, max_gens=3, ls_iters=20), 2 + 3 * (1 + 1 * 20)),
+             (dict(nrun=3, pop=5, ls_rate=0.4, max_gens=2, ls_iters=0), 5 + 2 * (4 + 2 * 0)),
+             (dict(nrun=2, pop=10, max_gens=5, max_evals=9), 10)]
+    for kw, per_run_evals in cases:
+        print("case", kw, flush=True)
+        r = ctx.ad_dock_batch(batch, small_params(pkg, **kw), 5, per_run=True)
+        nrun = kw["nrun"]
+        assert ctx.ad_get_schedule()["packed_runs"] == (nrun * packable if kw.get("ls_iters", 40) > 0 else 0), kw
+        assert np.all(r["evals"] == nrun * per_run_evals), kw
+        assert np.all(np.isfinite(r["run_energy"])), kw
+        for l in range(len(ligs)):
+            Er, _, _ = ctx.ad_score_poses(batch, np.full(nrun, l, np.int32), r["run_genotype"][l])
+            assert np.array_equal(Er, r["run_energy"][l]), (kw, spec[l])
+            Eo, _, To = orc.score(OL[l], G, r["best_genotype"][l].astype(np.float64))
+            assert abs(r["best_energy"][l] - Eo) <= max(E_ABS, E_REL * abs(Eo)), (kw, spec[l])
+            assert abs(r["best_score"][l] - To[2]) <= max(E_ABS, E_REL * abs(To[2])), (kw, spec[l])
+    batch.free()
