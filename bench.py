@@ -315,6 +315,73 @@ def screened_campaign(args, log_fn):
     return out
 
 
+def search_variants(ctx, batch, dock, infos, seed, plain, log_fn):
+    """The paper's other local search (Solis-Wets) and autostop, on the main
+    workload's ligands, receptor and search settings.
+
+    Solis-Wets runs a fixed number of generations without an evaluation cap,
+    so every run takes all of them and the local-search evaluations are the
+    total minus the GA's; its kernel is timed with HIP events like the
+    ADADELTA one (energy-only evaluations).  Autostop runs the ADADELTA
+    search of the main leg with per-run stopping and is compared with that
+    leg's timed step (same seed)."""
+    import numpy as np
+    import torch
+
+    import paper_2007_03678_amd as pkg
+
+    n_lig, nrun, pop = batch.n, dock["nrun"], dock["pop"]
+    n_ls = int(np.floor(dock["ls_rate"] * pop + 0.5))
+    G = 200
+    sw = dict(dock, ls_method=1, max_gens=G, max_evals=2 ** 62)
+    ctx.ad_dock_batch(batch, pkg.make_params(**dict(sw, max_gens=2)), seed)
+    ctx.ad_get_kernel_timing(reset=True)
+    ctx.ad_set_kernel_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = ctx.ad_dock_batch(batch, pkg.make_params(**sw), seed)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    kt = ctx.ad_get_kernel_timing(reset=True)
+    ctx.ad_set_kernel_timing(False)
+    assert np.all(r["generations"] == G)
+    ls_evals = r["evals"] - nrun * (pop + G * (pop - 1))
+    flop = sum(int(e) * flops_per_eval(i, False) for e, i in zip(ls_evals, infos))
+    ls_ms, ls_n = kt["ls"]
+    tf = flop / (ls_ms / 1e3) / 1e12
+    log_fn(f"solis-wets: {G} generations in {el:.2f}s, local-search kernel {tf:.2f} TFLOP/s")
+    out = {"solis_wets": {
+        "workload": (f"the main workload's ligands and grid, {nrun} runs x pop {pop}, Solis-Wets "
+                     f"(at most {dock['ls_iters']} evaluations) on {n_ls}/gen, {G} generations, no evaluation cap"),
+        "ligands_per_s": round(n_lig / el, 3),
+        "evals_per_s": round(float(r["evals"].sum()) / el, 1),
+        "ls_evals_per_search": round(float(ls_evals.sum()) / (n_lig * nrun * G * n_ls), 1),
+        "ls_kernel": "k_sw_generation (energy-only evaluations)",
+        "ls_kernel_tflops": round(tf, 3),
+        "frac": round(tf / PEAK_TFLOPS, 4),
+        "ls_kernel_ms_per_launch": round(ls_ms / max(ls_n, 1), 3),
+        "mean_best_energy": round(float(r["best_energy"].mean()), 3),
+    }}
+    # autostop on the main leg's search
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = ctx.ad_dock_batch(batch, pkg.make_params(**dict(dock, autostop=1)), seed)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    log_fn(f"autostop: {el:.2f}s")
+    out["autostop"] = {
+        "workload": "the main leg's docking with per-run autostop (std of the best energy over 10 generations "
+                    "below 0.15 kcal/mol)",
+        "ligands_per_s": round(n_lig / el, 4),
+        "speedup_vs_plain": round((n_lig / el) / plain["ligands_per_s"], 3),
+        "evals_frac_of_plain": round(float(r["evals"].sum()) / plain["evals"], 4),
+        "mean_generations_best_run": round(float(r["generations"].mean()), 1),
+        "generations_plain": plain["generations"],
+        "mean_best_energy_change": round(float((r["best_energy"] - plain["best_energy"]).mean()), 3),
+    }
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -325,6 +392,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-campaign", action="store_true", help="skip the plain-vs-screened campaign")
     ap.add_argument("--no-batch4096", action="store_true", help="skip the batched uneven docking leg")
+    ap.add_argument("--no-variants", action="store_true", help="skip the Solis-Wets and autostop measurements")
     ap.add_argument("--campaign-ligands", type=int, default=65536)
     ap.add_argument("--train-ligands", type=int, default=200_000)
     ap.add_argument("--label-gens", type=int, default=10)
@@ -459,6 +527,10 @@ def main():
                                        "packed_runs": schedule["packed_runs"]},
                        "graph_replay_ms_per_step": round(graph_ms, 2), "graph": schedule_graph["graph"]}
     out["score_grad_evals_per_s"] = round(dock["nrun"] * n_lig * n_ls * dock["ls_iters"] / ls_avg_s, 1)
+    if not args.no_variants:
+        plain = {"ligands_per_s": ligands_s, "evals": evals / args.steps, "best_energy": r["best_energy"],
+                 "generations": int(r["generations"][0])}
+        out["search_variants"] = search_variants(ctx, batch, dock, infos, seed, plain, log)
     batch.free()
     ctx.close()
     if not args.no_batch4096:
