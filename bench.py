@@ -67,6 +67,8 @@ def cpu_baseline(c, dock, seconds, log_fn):
     """The oracle docking ligand 0 of the workload with every host core, on a
     reduced evaluation cap per run; ligands/s extrapolated by evaluation
     count to the full configuration."""
+    import numpy as np
+
     import oracle
     import synth
     orc = oracle.Oracle(synth.forcefield())
@@ -92,11 +94,65 @@ def cpu_baseline(c, dock, seconds, log_fn):
     evals_s = ev.sum() / dt
     full_gens = min(dock["max_gens"], (dock["max_evals"] - pop) // per_gen)
     evals_per_ligand = nrun * (pop + full_gens * per_gen)
-    return dict(value=evals_s / evals_per_ligand, unit="ligands/s", cores=orc.max_threads(), kind="oracle",
+    # score + gradient evaluations of the same ligand on one core and on all
+    cores = orc.max_threads()
+    genos = synth.random_genotypes(5, 200_000, np.full(200_000, L.n_tor), c["grid"], margin=2.0)
+    rates = {}
+    for threads, n in ((1, 20_000), (cores, 200_000)):
+        t0 = time.time()
+        orc.score_batch([L], np.zeros(n, np.int32), G, genos[:n], threads=threads)
+        rates[threads] = n / (time.time() - t0)
+    log_fn(f"cpu baseline: score+gradient {rates[1]:.0f}/s on 1 core, {rates[cores]:.0f}/s on {cores}")
+    return dict(value=evals_s / evals_per_ligand, unit="ligands/s", cores=cores, kind="oracle",
                 evals_per_s=evals_s,
+                score_grad_evals_per_s={"1_core": round(rates[1], 1), f"{cores}_cores": round(rates[cores], 1)},
                 sample=(f"ligand 0 ({L.n} atoms, {L.n_tor} torsions), {nrun} runs x pop {pop}, {gens} "
                         f"generations ({int(ev.sum())} evaluations, {dt:.1f}s); ligands/s extrapolated by "
                         f"evaluation count to {evals_per_ligand} evaluations per ligand"))
+
+
+def score_leg(ctx, ligands, grid, log_fn, n=1 << 20):
+    """ad_score_poses with energy and gradient on n random poses per
+    atom-capacity bucket: each bucket's ligands loaded as a batch of their
+    own (a batch's score kernel is sized by its largest ligand), device
+    arrays so the timed call makes no host copies, the kernel timed with HIP
+    events."""
+    import numpy as np
+    import torch
+
+    import synth
+
+    nat = np.asarray(ligands.n_atoms_per_ligand)
+    out = {}
+    for name, sel in (("le64_atoms", np.flatnonzero(nat <= 64)), ("le128_atoms", np.flatnonzero(nat > 64))):
+        if len(sel) == 0:
+            continue
+        batch = ctx.ad_load_ligands(ligands.subset(sel))
+        infos = [batch.info(i) for i in range(batch.n)]
+        ntor = np.array([i["n_torsions"] for i in infos])
+        flop = np.array([flops_per_eval(i, True) for i in infos], dtype=np.float64)
+        idx = (np.arange(n) % batch.n).astype(np.int32)
+        genos = synth.random_genotypes(31, n, ntor[idx], grid, margin=2.0)
+        gd, idd = torch.from_numpy(genos).cuda(), torch.from_numpy(idx).cuda()
+        ctx.ad_score_poses(batch, idd[:4096], gd[:4096], grad=True)
+        ctx.ad_synchronize()
+        ctx.ad_get_kernel_timing(reset=True)
+        ctx.ad_set_kernel_timing(True)
+        t0 = time.perf_counter()
+        ctx.ad_score_poses(batch, idd, gd, grad=True)
+        ctx.ad_synchronize()
+        wall = time.perf_counter() - t0
+        kt = ctx.ad_get_kernel_timing(reset=True)
+        ctx.ad_set_kernel_timing(False)
+        ms = kt["score"][0]
+        tf = float(flop[idx].sum()) / (ms / 1e3) / 1e12
+        out[name] = {"poses": n, "ligands": int(batch.n), "kernel_ms": round(ms, 3), "wall_ms": round(wall * 1e3, 3),
+                     "score_grad_evals_per_s": round(n / (ms / 1e3), 1), "tflops": round(tf, 3),
+                     "frac": round(tf / PEAK_TFLOPS, 4)}
+        log_fn(f"score_poses {name}: {n} poses in {ms:.2f} ms, {tf:.2f} TFLOP/s")
+        del gd, idd
+        batch.free()
+    return out
 
 
 def batch_leg(args, log_fn):
@@ -114,7 +170,10 @@ def batch_leg(args, log_fn):
     c = synth.config("batch4096")
     ctx = pkg.create(synth.forcefield(), 0)
     ctx.ad_build_grids(c["grid"], c["receptor"])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
     batch = ctx.ad_load_ligands(c["ligands"])
+    load_s = time.perf_counter() - t1
     infos = [batch.info(i) for i in range(batch.n)]
     log_fn(f"batch4096: {batch.n} ligands generated and loaded in {time.time() - t0:.1f}s")
     dock = c["dock"]
@@ -137,6 +196,8 @@ def batch_leg(args, log_fn):
                      f"{max(i['n_atoms'] for i in infos)}, lognormal median 32; torsions 0-32), 8,000-atom receptor, "
                      f"80^3 x 10 FP32 maps, {dock['nrun']} runs x pop {dock['pop']}, cap {dock['max_evals']} evals/run"),
         "ligands_per_s": round(batch.n / dt, 3),
+        "ligands_per_s_with_load": round(batch.n / (dt + load_s), 3),
+        "load_s": round(load_s, 3),
         "evals_per_s": round(float(r["evals"].sum()) / dt, 1),
         "step_s": round(dt, 2),
         "generations": int(r["generations"][0]),
@@ -148,6 +209,7 @@ def batch_leg(args, log_fn):
     }
     log_fn(f"batch4096: docked in {dt:.1f}s")
     batch.free()
+    out["score_poses"] = score_leg(ctx, c["ligands"], c["grid"], log_fn)
     # the same ligands streamed in batches of 1,024: host preparation and
     # upload of the next batch overlap the docking of the current one
     torch.cuda.synchronize()

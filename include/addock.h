@@ -179,7 +179,10 @@ int ad_batch_info(const ad_batch *b, int lig, int *n_atoms, int *n_torsions, int
  *   q <- exp(omega/2) q.
  *   terms (optional, [n][3]) = {inter, intra, score = inter + w_tor*T}.
  * Pure and deterministic.  A non-finite genotype gives NaN outputs (not an
- * error).  Errors: AD_E_INVALID (bad lig_idx, n < 0), AD_E_STATE. */
+ * error).  Errors: AD_E_INVALID (bad lig_idx, n < 0), AD_E_STATE.
+ * One 64-lane work-group per pose, sized by the batch's largest ligand (up
+ * to 64 or up to 128 atoms), so a batch of small ligands alone scores
+ * faster than the same ligands in a batch that also holds large ones. */
 int ad_score_poses(ad_ctx *ctx, const ad_batch *b, int n, const int *lig_idx, const float *genotypes,
                    float *energy, float *grad, float *terms, int ptrs_on_device);
 
