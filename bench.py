@@ -564,6 +564,7 @@ def main():
                          f"x pop {dock['pop']}, cap {dock['max_evals']} evals/run, ADADELTA "
                          f"{dock['ls_iters']} it on {n_ls}/gen"),
             "n_ligands": n_lig, "nrun": dock["nrun"], "pop": dock["pop"], "max_evals_per_run": dock["max_evals"],
+            "seeds": {"inputs": c["seed"], "docking": seed},
             "generations": int(r["generations"][0]),
         },
         "evals_per_s": round(evals_s, 1),
