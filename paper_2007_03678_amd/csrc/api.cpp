@@ -409,7 +409,7 @@ int load_ligands_impl(ad_ctx *c, int n, const ad_ligand *ligs, uint64_t uid, ad_
     tors.insert(tors.end(), P.tors.begin(), P.tors.end());
     if (P.n_atoms > 64) cap = 128;
   }
-  pairs.resize(pairs.size() + kWave, PairRec{0, 0.0f, 0.0f, 0.0f});   // spare records: the kernels prefetch 64 ahead
+  pairs.resize(pairs.size() + 2 * kWave, PairRec{0, 0.0f, 0.0f, 0.0f});   // spare records: the kernels prefetch 128 ahead
   b->cap = cap;
   b->lig_host = lig;
   b->depth_sum.resize(n);

@@ -504,14 +504,24 @@ __device__ double evaluate(const EvalConst &C, const LaneLig<CAP> &LL, EvalLds<C
   extern __shared__ __attribute__((aligned(16))) char dyn_lds[];
   const LJRec *s_lj = reinterpret_cast<const LJRec *>(dyn_lds + st.off);
   const PairRec *s_pr = reinterpret_cast<const PairRec *>(dyn_lds + st.off + C.ff.n_types * C.ff.n_types * 16);
-  PairRec rec_next;
-  if (lane < L.n_pairs) rec_next = (STAGE && lane < st.n) ? s_pr[lane] : pr[lane];
+  // two-deep prefetch: the record of the step after next is loaded while the
+  // type-pair record of the next step is fetched with the next record (which
+  // arrived one step earlier), so neither load waits at its use.  The batch's
+  // pair array ends with 128 spare records, so these loads stay in bounds;
+  // past the ligand's list they read records that are not used
+  PairRec rec_a, rec_b;
+  LJRec lj_a;
+  if (lane < L.n_pairs) {
+    rec_a = (STAGE && lane < st.n) ? s_pr[lane] : pr[lane];
+    rec_b = (STAGE && lane + W < st.n) ? s_pr[lane + W] : pr[lane + W];
+    lj_a = STAGE ? s_lj[rec_a.ijt >> 16] : ljt[rec_a.ijt >> 16];
+  }
   for (int p = lane; p < L.n_pairs; p += W) {
-    const PairRec rec = rec_next;
-    // the batch's pair array ends with 64 spare records, so this prefetch
-    // stays in bounds; past the ligand's list it reads a record not used
-    rec_next = (STAGE && p + W < st.n) ? s_pr[p + W] : pr[p + W];
-    const LJRec lj = STAGE ? s_lj[rec.ijt >> 16] : ljt[rec.ijt >> 16];
+    const PairRec rec = rec_a;
+    const LJRec lj = lj_a;
+    rec_a = rec_b;
+    rec_b = (STAGE && p + 2 * W < st.n) ? s_pr[p + 2 * W] : pr[p + 2 * W];
+    lj_a = STAGE ? s_lj[rec_a.ijt >> 16] : ljt[rec_a.ijt >> 16];
     const int i = rec.ijt & 0xff, j = (rec.ijt >> 8) & 0xff;
     const double dx = S.x[0][i] - S.x[0][j], dy = S.x[1][i] - S.x[1][j], dz = S.x[2][i] - S.x[2][j];
     const float r2 = (float)(dx * dx + dy * dy + dz * dz);
