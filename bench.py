@@ -30,22 +30,28 @@ def log(*a):
 
 
 def flops_per_eval(info, grad):
-    """Algorithmic FLOP of one evaluation of a ligand (see the derivation of
-    the per-term counts in the design notes): pairs, atoms, torsion-moved
-    atoms, torsions."""
+    """Algorithmic FLOP of one evaluation of a ligand, counted from the
+    scoring function's formulas (add, sub, mul 1; FMA 2; each transcendental
+    1).  With the gradient: per pair 62 (distance 9, smoothing 2, 12-6/12-10
+    14, electrostatics 17, desolvation 5, totals 5, force 9, accumulation 1);
+    per atom 129 (grid coordinates 9, corner values 32, interpolation 24, its
+    gradient 27, accumulation 1, global transform 18, torque 18); per atom and
+    torsion moving it 33 (rotation 18, torsion torque 15); per torsion 38
+    (sin/cos and rotation matrix 22, axis and projection 16); per pose 40
+    (quaternion normalisation and matrix).  Energy only: 36, 84, 18, 22, 40."""
     P, N, T, D = info["n_pairs"], info["n_atoms"], info["n_torsions"], info["depth_sum"]
     if grad:
         return 62 * P + 129 * N + 33 * D + 38 * T + 40
     return 36 * P + 84 * N + 18 * D + 22 * T + 40
 
 
-def measured_traffic():
+def measured_traffic(path=None, src=None):
     """HBM bytes per launch of the local-search kernel from the committed
     rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None once the kernel
     source differs from the one the counters were taken on."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_ls_generation_screen64.md")
-    src = os.path.join(ROOT, "paper_2007_03678_amd", "csrc", "kernels.hip")
+    path = path or os.path.join(ROOT, "profiles", "k_ls_generation_screen64.md")
+    src = src or os.path.join(ROOT, "paper_2007_03678_amd", "csrc", "kernels.hip")
     try:
         fields = dict(line.split(": ", 1) for line in open(path).read().splitlines()
                       if line.startswith("traffic_"))
@@ -470,8 +476,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "the docking path runs on one GPU; --gpus must be 1 (the workload would "
-                                   "shard by ligand across GPUs, see the design notes)", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "the docking path runs on one GPU; --gpus must be 1 (across GPUs the "
+                                   "workload would shard by ligand, each GPU holding its own copy of the maps)", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import numpy as np

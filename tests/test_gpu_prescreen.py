@@ -3,7 +3,11 @@
 The oracle rounds to BF16 at the same points as the GPU path, so the two
 differ only by accumulation order (FP32 MFMA sums and FP32 neighbour/pool
 sums against FP64) and by the rare BF16 rounding that this order flips.
-Tolerances (derived in the design notes):
+An activation is the BF16 rounding of a sum of K <= 256 terms whose FP32 and
+FP64 values differ by about sqrt(K) 2^-24 of the terms' scale, so roughly
+K 2^-16 (under 0.4 %) of activations fall on the other side of a BF16
+rounding midpoint and differ by one BF16 ulp (2^-8 relative); such flips are
+isolated and add incoherently.  Tolerances:
   predictions:  ||p_gpu - p_orc||_2 <= 2e-3 ||p_orc||_2; >= 90% of graphs within
                 1e-4 max(|p|, 1) and every graph within 2e-2 max(rms p, 1)
   loss:         relative 2e-3
