@@ -103,8 +103,10 @@ typedef struct {
  * the stream all work is queued on.  No GPU -> AD_E_DEVICE; malformed force
  * field -> AD_E_INVALID.  Device memory is owned by the context and freed by
  * ad_destroy (which first waits for the stream).  Batches (ad_load_ligands)
- * and pre-screens (ad_prescreen_create) refer to their context: free them
- * before the context; using or freeing one after ad_destroy is undefined. */
+ * and pre-screens (ad_prescreen_create) belong to their context, in any
+ * teardown order: ad_destroy releases the device memory of those still alive
+ * and detaches them, after which ad_free_batch / ad_prescreen_destroy only
+ * delete the handle and every other call with them returns AD_E_INVALID. */
 int ad_create(ad_ctx **out, int device, const ad_forcefield *ff, void *hip_stream);
 void ad_destroy(ad_ctx *ctx);
 const char *ad_last_error(const ad_ctx *ctx);
@@ -121,9 +123,14 @@ int ad_synchronize(ad_ctx *ctx);
  * k_out*|x - x_clamped|^2 is added.  The library copies the maps (host or
  * device source) and keeps them resident until the next load or destroy.
  * Errors: AD_E_INVALID (dims < 2, spacing <= 0, bad map types, non-finite
- * values, nx*ny >= 2^24 or n_maps*nx*ny*nz >= 2^32: the kernels index map
- * records in 32 bits), AD_E_OOM. */
+ * values, nx*ny >= 2^24, n_maps*nz >= 2^24 or n_maps*nx*ny*nz >= 2^32: the
+ * kernels index map records in 32 bits with 24-bit products), AD_E_OOM. */
 int ad_load_grids(ad_ctx *ctx, const ad_grid_desc *g, const float *maps, int ptrs_on_device);
+/* ad_grid_check: the host-only validation of ad_load_grids (geometry, map
+ * types against a force field with n_types types, index limits); no context
+ * or GPU needed.  Returns AD_OK or AD_E_INVALID with a message in msg (if
+ * msg_len > 0). */
+int ad_grid_check(const ad_grid_desc *g, int n_types, char *msg, int msg_len);
 
 /* ad_build_grids: computes the maps on the GPU from receptor atoms (host
  * arrays: xyz [n_rec][3], type ids, charges) by direct sums in the same
@@ -185,6 +192,31 @@ int ad_batch_info(const ad_batch *b, int lig, int *n_atoms, int *n_torsions, int
  * faster than the same ligands in a batch that also holds large ones. */
 int ad_score_poses(ad_ctx *ctx, const ad_batch *b, int n, const int *lig_idx, const float *genotypes,
                    float *energy, float *grad, float *terms, int ptrs_on_device);
+
+/* Evaluation shapes: the kernel variant that evaluates a pose.  Every shape
+ * computes the same function within the stated tolerance; they differ in
+ * the order of the FP64 sums (the last bits) and in speed.
+ *   AD_SHAPE_AUTO     the batch's default: AD_SHAPE_WAVE64 when every ligand
+ *                     of the batch has at most 64 atoms, else AD_SHAPE_WAVE128
+ *   AD_SHAPE_WAVE64   one 64-lane wavefront per pose, one atom per lane
+ *                     (ligands of at most 64 atoms)
+ *   AD_SHAPE_WAVE128  one wavefront per pose, two atoms per lane (<= 128)
+ *   AD_SHAPE_PACKED   two poses per wavefront, one per 32-lane half (ligands
+ *                     of at most 32 atoms and 25 torsions) -- the evaluation
+ *                     the docking search uses for the local search of small
+ *                     ligands; poses 2w and 2w+1 share wavefront w and must
+ *                     name the same ligand.
+ * ad_score_poses_shape / ad_local_search_shape: ad_score_poses /
+ * ad_local_search evaluated with the given shape.  A pose whose ligand does
+ * not fit the shape (or, packed, whose partner names another ligand) is
+ * AD_E_INVALID with host indices and gives NaN with device indices; an
+ * unknown shape is AD_E_INVALID. */
+#define AD_SHAPE_AUTO 0
+#define AD_SHAPE_WAVE64 1
+#define AD_SHAPE_WAVE128 2
+#define AD_SHAPE_PACKED 3
+int ad_score_poses_shape(ad_ctx *ctx, const ad_batch *b, int n, const int *lig_idx, const float *genotypes,
+                         float *energy, float *grad, float *terms, int ptrs_on_device, int shape);
 
 /* ---- docking: Lamarckian GA + ADADELTA (Sec. 1, Sec. 1.1) ----------------
  * Per ligand, nrun independent runs.  Generation 0 evaluates pop random
@@ -260,6 +292,8 @@ int ad_dock_select(ad_ctx *ctx, const ad_batch *b, int n, const int *lig_idx, co
  * pose and energy its energy (Lamarckian write-back).  Uses p->rho, p->eps. */
 int ad_local_search(ad_ctx *ctx, const ad_batch *b, int n, const int *lig_idx, float *genotypes, float *energy,
                     const ad_dock_params *p, int iters, int ptrs_on_device);
+int ad_local_search_shape(ad_ctx *ctx, const ad_batch *b, int n, const int *lig_idx, float *genotypes,
+                          float *energy, const ad_dock_params *p, int iters, int ptrs_on_device, int shape);
 
 /* ad_solis_wets: Solis-Wets local search (parameters sw_* of p) on n given
  * poses (host arrays: lig_idx [n], genotypes [n][40] in/out, energy [n]

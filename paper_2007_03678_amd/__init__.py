@@ -7,9 +7,11 @@ provides device memory and streams).  The library must be built
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
 import subprocess
+import sys
 import weakref
 
 import numpy as np
@@ -23,10 +25,11 @@ AD_OK, AD_E_INVALID, AD_E_NOMAP, AD_E_OOM, AD_E_DEVICE, AD_E_STATE, AD_E_UNSUPPO
 ERR_NAMES = {0: "AD_OK", -1: "AD_E_INVALID", -2: "AD_E_NOMAP", -3: "AD_E_OOM", -4: "AD_E_DEVICE",
              -5: "AD_E_STATE", -6: "AD_E_UNSUPPORTED", -7: "AD_E_HIP"}
 MAX_TYPES, STRIDE = 16, 40
+SHAPE_AUTO, SHAPE_WAVE64, SHAPE_WAVE128, SHAPE_PACKED = 0, 1, 2, 3
 
 EXPORTS = ["ad_create", "ad_destroy", "ad_last_error", "ad_set_stream", "ad_synchronize", "ad_load_grids",
-           "ad_build_grids", "ad_ligand_check", "ad_load_ligands", "ad_load_ligands_packed", "ad_free_batch", "ad_dock_stream", "ad_batch_info",
-           "ad_score_poses", "ad_dock_batch", "ad_dock_select", "ad_local_search", "ad_solis_wets", "ad_initial_population",
+           "ad_build_grids", "ad_grid_check", "ad_ligand_check", "ad_load_ligands", "ad_load_ligands_packed", "ad_free_batch", "ad_dock_stream", "ad_batch_info",
+           "ad_score_poses", "ad_score_poses_shape", "ad_dock_batch", "ad_dock_select", "ad_local_search", "ad_local_search_shape", "ad_solis_wets", "ad_initial_population",
            "ad_set_kernel_timing", "ad_get_kernel_timing", "ad_set_schedule", "ad_get_schedule",
            "ad_prescreen_n_params", "ad_prescreen_create",
            "ad_prescreen_destroy", "ad_prescreen_set_params", "ad_prescreen_get_params", "ad_prescreen_set_scale",
@@ -140,6 +143,7 @@ def lib():
     L.ad_load_grids.argtypes = [vp, C.POINTER(GridDesc), vp, C.c_int]
     L.ad_build_grids.argtypes = [vp, C.POINTER(GridDesc), C.c_int, fp, ip, fp, fp]
     L.ad_ligand_check.argtypes = [C.POINTER(Ligand), C.c_int, C.c_char_p, C.c_int]
+    L.ad_grid_check.argtypes = [C.POINTER(GridDesc), C.c_int, C.c_char_p, C.c_int]
     L.ad_load_ligands.argtypes = [vp, C.c_int, C.POINTER(Ligand), C.POINTER(vp)]
     L.ad_load_ligands_packed.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp, vp, vp, C.POINTER(vp)]
     L.ad_dock_stream.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp, vp, vp, C.c_int, C.POINTER(DockParams),
@@ -150,6 +154,9 @@ def lib():
     L.ad_set_kernel_timing.argtypes = [vp, C.c_int]
     L.ad_get_kernel_timing.argtypes = [vp, C.POINTER(KernelTimes), C.c_int]
     L.ad_score_poses.argtypes = [vp, vp, C.c_int, vp, vp, vp, vp, vp, C.c_int]
+    L.ad_score_poses_shape.argtypes = [vp, vp, C.c_int, vp, vp, vp, vp, vp, C.c_int, C.c_int]
+    L.ad_local_search_shape.argtypes = [vp, vp, C.c_int, vp, vp, vp, C.POINTER(DockParams), C.c_int, C.c_int,
+                                        C.c_int]
     L.ad_dock_batch.argtypes = [vp, vp, C.POINTER(DockParams), C.c_uint64, vp, C.POINTER(DockResult), fp, fp]
     L.ad_dock_select.argtypes = [vp, vp, C.c_int, vp, C.POINTER(DockParams), C.c_uint64, C.POINTER(DockResult), fp,
                                  fp]
@@ -244,6 +251,14 @@ def ad_ligand_check(lig, n_types: int):
     return rc, buf.value.decode()
 
 
+def ad_grid_check(grid, n_types: int):
+    """Host-only grid validation; returns (code, message)."""
+    d, keep = _grid_desc(grid)
+    buf = C.create_string_buffer(256)
+    rc = lib().ad_grid_check(C.byref(d), n_types, buf, 256)
+    return rc, buf.value.decode()
+
+
 def _grid_desc(grid):
     mt = (C.c_int * max(1, len(grid.map_types)))(*grid.map_types)
     d = GridDesc()
@@ -276,8 +291,27 @@ class Batch:
             self.h = None
 
     def __del__(self):
+        # at interpreter shutdown the HIP runtime may already be gone: the
+        # process is ending and the driver reclaims the memory
+        if sys.is_finalizing():
+            return
         try:
             self.free()
+        except Exception:
+            pass
+
+
+_live_contexts = weakref.WeakSet()
+_atexit_registered = False
+
+
+def _close_all_contexts():
+    """atexit: close live contexts (their batches and pre-screens first)
+    while the HIP runtime is still up.  Registered after torch is imported,
+    so it runs before torch's own exit handlers."""
+    for ctx in list(_live_contexts):
+        try:
+            ctx.close()
         except Exception:
             pass
 
@@ -298,6 +332,11 @@ class Context:
         if rc:
             raise AddockError(rc, "ad_create failed")
         self.h = h
+        global _atexit_registered
+        _live_contexts.add(self)
+        if not _atexit_registered:
+            atexit.register(_close_all_contexts)
+            _atexit_registered = True
 
     def _check(self, rc):
         if rc:
@@ -371,8 +410,13 @@ class Context:
                                                  _ptr(bd), _ptr(rot), C.byref(h)))
         return Batch(self, h, len(na))
 
-    def ad_score_poses(self, batch, lig_idx, genotypes, grad=False, terms=False, out=None):
-        """Host (numpy) or device (torch CUDA) arrays.  Returns (energy, grad, terms)."""
+    def ad_score_poses(self, batch, lig_idx, genotypes, grad=False, terms=False, out=None, shape=None):
+        """Host (numpy) or device (torch CUDA) arrays.  Returns (energy, grad, terms).
+        shape: None (ad_score_poses) or an AD_SHAPE_* value (ad_score_poses_shape)."""
+        def call(*a):
+            if shape is None:
+                return lib().ad_score_poses(*a)
+            return lib().ad_score_poses_shape(*a, int(shape))
         if _is_device(genotypes):
             import torch
             n = genotypes.shape[0]
@@ -381,8 +425,7 @@ class Context:
                                                      device=genotypes.device)) if grad else None
             T = (out["terms"] if out else torch.empty((n, 3), dtype=torch.float32,
                                                       device=genotypes.device)) if terms else None
-            self._check(lib().ad_score_poses(self.h, batch.h, n, _ptr(lig_idx), _ptr(genotypes), _ptr(E),
-                                             _ptr(G), _ptr(T), 1))
+            self._check(call(self.h, batch.h, n, _ptr(lig_idx), _ptr(genotypes), _ptr(E), _ptr(G), _ptr(T), 1))
             return E, G, T
         g = _np(genotypes, np.float32)
         n = g.shape[0]
@@ -390,24 +433,27 @@ class Context:
         E = np.empty(n, np.float32)
         G = np.empty((n, STRIDE), np.float32) if grad else None
         T = np.empty((n, 3), np.float32) if terms else None
-        self._check(lib().ad_score_poses(self.h, batch.h, n, _ptr(idx), _ptr(g), _ptr(E), _ptr(G), _ptr(T), 0))
+        self._check(call(self.h, batch.h, n, _ptr(idx), _ptr(g), _ptr(E), _ptr(G), _ptr(T), 0))
         return E, G, T
 
-    def ad_local_search(self, batch, lig_idx, genotypes, params: DockParams, iters: int):
-        """Host arrays: returns (best genotypes, energies); device tensors are updated in place."""
+    def ad_local_search(self, batch, lig_idx, genotypes, params: DockParams, iters: int, shape=None):
+        """Host arrays: returns (best genotypes, energies); device tensors are updated in place.
+        shape: None (ad_local_search) or an AD_SHAPE_* value (ad_local_search_shape)."""
+        def call(*a):
+            if shape is None:
+                return lib().ad_local_search(*a)
+            return lib().ad_local_search_shape(*a, int(shape))
         if _is_device(genotypes):
             import torch
             n = genotypes.shape[0]
             E = torch.empty(n, dtype=torch.float32, device=genotypes.device)
-            self._check(lib().ad_local_search(self.h, batch.h, n, _ptr(lig_idx), _ptr(genotypes), _ptr(E),
-                                              C.byref(params), iters, 1))
+            self._check(call(self.h, batch.h, n, _ptr(lig_idx), _ptr(genotypes), _ptr(E), C.byref(params), iters, 1))
             return genotypes, E
         g = _np(genotypes, np.float32).copy()
         n = g.shape[0]
         idx = _np(lig_idx, np.int32)
         E = np.empty(n, np.float32)
-        self._check(lib().ad_local_search(self.h, batch.h, n, _ptr(idx), _ptr(g), _ptr(E), C.byref(params),
-                                          iters, 0))
+        self._check(call(self.h, batch.h, n, _ptr(idx), _ptr(g), _ptr(E), C.byref(params), iters, 0))
         return g, E
 
     def ad_solis_wets(self, batch, lig_idx, genotypes, params: DockParams, max_evals: int, seed: int):
@@ -487,6 +533,9 @@ class Context:
         return g
 
     def close(self):
+        """Free the batches and pre-screens still open, then the context.  The
+        library detaches any child it still finds, so the order is not needed
+        for safety; it only releases their memory early."""
         if getattr(self, "h", None):
             for child in list(self._children):
                 child.close() if isinstance(child, Prescreen) else child.free()
@@ -494,6 +543,8 @@ class Context:
             self.h = None
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -571,6 +622,8 @@ class Prescreen:
             self.h = None
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:

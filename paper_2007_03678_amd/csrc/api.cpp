@@ -121,9 +121,12 @@ static int check_grid_desc(const ad_grid_desc *g, int n_types, std::string *msg)
   if (!g) return *msg = "null grid descriptor", AD_E_INVALID;
   if (g->nx < 2 || g->ny < 2 || g->nz < 2) return *msg = "grid needs >= 2 points per axis", AD_E_INVALID;
   if ((double)g->nx * g->ny * g->nz > 2.0e9) return *msg = "grid too large", AD_E_INVALID;
-  // the kernels index the map records in 32 bits (24-bit products)
-  if ((double)g->nx * g->ny >= 16777216.0 || (double)std::max(g->n_maps, 1) * g->nx * g->ny * g->nz >= 4294967296.0)
-    return *msg = "grid too large for the map indexing (nx*ny < 2^24, n_maps*nx*ny*nz < 2^32)", AD_E_INVALID;
+  // the kernels index the map records in 32 bits with 24-bit products:
+  // (m * nz + k) * (nx * ny) + j * nx + i, both factors below 2^24
+  if ((double)g->nx * g->ny >= 16777216.0 || (double)std::max(g->n_maps, 1) * g->nz >= 16777216.0 ||
+      (double)std::max(g->n_maps, 1) * g->nx * g->ny * g->nz >= 4294967296.0)
+    return *msg = "grid too large for the map indexing (nx*ny < 2^24, n_maps*nz < 2^24, n_maps*nx*ny*nz < 2^32)",
+           AD_E_INVALID;
   if (!(g->spacing > 0) || !finite_d(g->spacing)) return *msg = "spacing must be > 0", AD_E_INVALID;
   for (int d = 0; d < 3; ++d)
     if (!finite_d(g->origin[d])) return *msg = "non-finite origin", AD_E_INVALID;
@@ -135,6 +138,22 @@ static int check_grid_desc(const ad_grid_desc *g, int n_types, std::string *msg)
       if (g->map_types[k] == g->map_types[m]) return *msg = "duplicate map type", AD_E_INVALID;
   }
   return AD_OK;
+}
+
+extern "C" int ad_grid_check(const ad_grid_desc *g, int n_types, char *msg, int msg_len) {
+  std::string err;
+  int rc = AD_OK;
+  if (n_types < 1 || n_types > AD_MAX_TYPES) {
+    rc = AD_E_INVALID;
+    err = "n_types must be 1..16";
+  } else {
+    rc = check_grid_desc(g, n_types, &err);
+  }
+  if (msg && msg_len > 0) {
+    strncpy(msg, rc ? err.c_str() : "", (size_t)msg_len - 1);
+    msg[msg_len - 1] = 0;
+  }
+  return rc;
 }
 
 // ---------------------------------------------------------------------------
@@ -193,6 +212,18 @@ extern "C" void ad_destroy(ad_ctx *c) {
   if (!c) return;
   hipSetDevice(c->device);
   if (c->stream) hipStreamSynchronize(c->stream);
+  {
+    // children still alive give up their device memory and their link to
+    // the context; freeing them later only deletes the handle
+    std::lock_guard<std::mutex> lk(c->child_mu);
+    for (ad_batch *b : c->batches) {
+      batch_release(b);
+      b->ctx = nullptr;
+    }
+    for (ad_prescreen *ps : c->prescreens) prescreen_release(ps);
+    c->batches.clear();
+    c->prescreens.clear();
+  }
   for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
   if (c->maps4) hipFree(c->maps4);
   if (c->lj_dev) hipFree(c->lj_dev);
@@ -455,6 +486,7 @@ int load_ligands_impl(ad_ctx *c, int n, const ad_ligand *ligs, uint64_t uid, ad_
     *err = "cannot upload ligand batch";
     return AD_E_OOM;
   }
+  register_batch(c, b);
   *out = b;
   return AD_OK;
 }
@@ -514,17 +546,39 @@ extern "C" int ad_load_ligands_packed(ad_ctx *c, int n, const int *n_atoms, cons
   return ad_load_ligands(c, n, v.data(), out);
 }
 
-extern "C" void ad_free_batch(ad_batch *b) {
-  if (!b) return;
+void register_batch(ad_ctx *c, ad_batch *b) {
+  std::lock_guard<std::mutex> lk(c->child_mu);
+  c->batches.insert(b);
+}
+
+void unregister_batch(ad_ctx *c, ad_batch *b) {
+  std::lock_guard<std::mutex> lk(c->child_mu);
+  c->batches.erase(b);
+}
+
+// Frees the batch's device memory (the host descriptors stay readable).
+void batch_release(ad_batch *b) {
   hipSetDevice(b->device);
   if (b->ctx && b->ctx->stream) hipStreamSynchronize(b->ctx->stream);
-  hipFree(b->lig);
-  hipFree(b->geo);
-  hipFree(b->info);
-  hipFree(b->pairs);
-  hipFree(b->tors);
-  hipFree(b->ps_x);
-  hipFree(b->ps_nbr);
+  void *bufs[] = {b->lig, b->geo, b->info, b->pairs, b->tors, b->ps_x, b->ps_nbr};
+  for (void *p : bufs)
+    if (p) hipFree(p);
+  b->lig = nullptr;
+  b->geo = nullptr;
+  b->info = nullptr;
+  b->pairs = nullptr;
+  b->tors = nullptr;
+  b->ps_x = nullptr;
+  b->ps_nbr = nullptr;
+}
+
+extern "C" void ad_free_batch(ad_batch *b) {
+  if (!b) return;
+  // a batch detached by ad_destroy has no device memory left
+  if (b->ctx) {
+    unregister_batch(b->ctx, b);
+    batch_release(b);
+  }
   delete b;
 }
 
@@ -545,7 +599,7 @@ extern "C" int ad_batch_info(const ad_batch *b, int lig, int *n_atoms, int *n_to
 // ---------------------------------------------------------------------------
 static int check_batch(ad_ctx *c, const ad_batch *b) {
   if (!b) return c->fail(AD_E_INVALID, "null batch");
-  if (b->ctx != c) return c->fail(AD_E_INVALID, "batch belongs to another context");
+  if (b->ctx != c) return c->fail(AD_E_INVALID, "batch belongs to another (or a destroyed) context");
   if (!c->has_grid) return c->fail(AD_E_STATE, "no grid loaded");
   // the batch's atoms carry map indices: the resident grid must still assign them
   for (int t = 0; t < AD_MAX_TYPES; ++t)
@@ -554,24 +608,58 @@ static int check_batch(ad_ctx *c, const ad_batch *b) {
   return AD_OK;
 }
 
+// Kernel atom capacity of an evaluation shape (32: the packed kernels), or
+// -1 for an unknown shape.
+static int shape_cap(const ad_batch *b, int shape) {
+  switch (shape) {
+    case AD_SHAPE_AUTO: return b->cap;
+    case AD_SHAPE_WAVE64: return 64;
+    case AD_SHAPE_WAVE128: return 128;
+    case AD_SHAPE_PACKED: return 32;
+    default: return -1;
+  }
+}
+
+// Host-side check of the ligands a shaped call names (host index arrays).
+static int check_shape_poses(ad_ctx *c, const ad_batch *b, int n, const int *lig_idx, int shape) {
+  for (int p = 0; p < n; ++p)
+    if (lig_idx[p] < 0 || lig_idx[p] >= b->n_lig) return c->fail(AD_E_INVALID, "lig_idx out of range");
+  const int cap = shape_cap(b, shape);
+  for (int p = 0; p < n; ++p) {
+    const LigDesc &d = b->lig_host[lig_idx[p]];
+    if (d.n_atoms > std::max(cap, kDualAtoms) || (cap == kDualAtoms && d.n_tor > kDualTor))
+      return c->fail(AD_E_INVALID, "pose " + std::to_string(p) + ": ligand too large for the evaluation shape");
+    if (shape == AD_SHAPE_PACKED && (p & 1) && lig_idx[p] != lig_idx[p - 1])
+      return c->fail(AD_E_INVALID, "packed shape: poses 2w and 2w+1 must name the same ligand");
+  }
+  return AD_OK;
+}
+
 extern "C" int ad_score_poses(ad_ctx *c, const ad_batch *b, int n, const int *lig_idx, const float *genotypes,
                               float *energy, float *grad, float *terms, int ptrs_on_device) {
+  return ad_score_poses_shape(c, b, n, lig_idx, genotypes, energy, grad, terms, ptrs_on_device, AD_SHAPE_AUTO);
+}
+
+extern "C" int ad_score_poses_shape(ad_ctx *c, const ad_batch *b, int n, const int *lig_idx, const float *genotypes,
+                                    float *energy, float *grad, float *terms, int ptrs_on_device, int shape) {
   if (!c) return AD_E_INVALID;
   int rc = check_batch(c, b);
   if (rc) return rc;
   if (n < 0) return c->fail(AD_E_INVALID, "n < 0");
+  const int cap = shape_cap(b, shape);
+  if (cap < 0) return c->fail(AD_E_INVALID, "unknown evaluation shape");
   if (n == 0) return AD_OK;
   if (!lig_idx || !genotypes || !energy) return c->fail(AD_E_INVALID, "null argument");
   hipSetDevice(c->device);
   const EvalConst C = c->eval_const(b);
   if (ptrs_on_device) {
     const int t0 = c->timing_begin(3);
-    HIP_TRY(c, launch_score(C, b->cap, n, lig_idx, genotypes, energy, grad, terms, c->stream));
+    HIP_TRY(c, launch_score(C, cap, n, lig_idx, genotypes, energy, grad, terms, c->stream));
     c->timing_end(3, t0);
     return AD_OK;
   }
-  for (int p = 0; p < n; ++p)
-    if (lig_idx[p] < 0 || lig_idx[p] >= b->n_lig) return c->fail(AD_E_INVALID, "lig_idx out of range");
+  rc = check_shape_poses(c, b, n, lig_idx, shape);
+  if (rc) return rc;
   const size_t nb_idx = ((size_t)n * 4 + 255) & ~(size_t)255;
   const size_t nb_geo = ((size_t)n * kStride * 4 + 255) & ~(size_t)255;
   const size_t nb_e = ((size_t)n * 4 + 255) & ~(size_t)255;
@@ -587,7 +675,7 @@ extern "C" int ad_score_poses(ad_ctx *c, const ad_batch *b, int n, const int *li
   HIP_TRY(c, hipMemcpyAsync(d_idx, lig_idx, (size_t)n * 4, hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipMemcpyAsync(d_geo, genotypes, (size_t)n * kStride * 4, hipMemcpyHostToDevice, c->stream));
   const int t0 = c->timing_begin(3);
-  HIP_TRY(c, launch_score(C, b->cap, n, d_idx, d_geo, d_e, d_g, d_t, c->stream));
+  HIP_TRY(c, launch_score(C, cap, n, d_idx, d_geo, d_e, d_g, d_t, c->stream));
   c->timing_end(3, t0);
   HIP_TRY(c, hipMemcpyAsync(energy, d_e, (size_t)n * 4, hipMemcpyDeviceToHost, c->stream));
   if (grad) HIP_TRY(c, hipMemcpyAsync(grad, d_g, (size_t)n * kStride * 4, hipMemcpyDeviceToHost, c->stream));
@@ -599,23 +687,31 @@ extern "C" int ad_score_poses(ad_ctx *c, const ad_batch *b, int n, const int *li
 
 extern "C" int ad_local_search(ad_ctx *c, const ad_batch *b, int n, const int *lig_idx, float *genotypes,
                                float *energy, const ad_dock_params *p, int iters, int ptrs_on_device) {
+  return ad_local_search_shape(c, b, n, lig_idx, genotypes, energy, p, iters, ptrs_on_device, AD_SHAPE_AUTO);
+}
+
+extern "C" int ad_local_search_shape(ad_ctx *c, const ad_batch *b, int n, const int *lig_idx, float *genotypes,
+                                     float *energy, const ad_dock_params *p, int iters, int ptrs_on_device,
+                                     int shape) {
   if (!c) return AD_E_INVALID;
   int rc = check_batch(c, b);
   if (rc) return rc;
   if (n < 0 || iters < 0 || !p) return c->fail(AD_E_INVALID, "bad local-search arguments");
   if (!(p->rho >= 0 && p->rho < 1) || !(p->eps > 0)) return c->fail(AD_E_INVALID, "bad ADADELTA rho / eps");
+  const int cap = shape_cap(b, shape);
+  if (cap < 0) return c->fail(AD_E_INVALID, "unknown evaluation shape");
   if (n == 0) return AD_OK;
   if (!lig_idx || !genotypes || !energy) return c->fail(AD_E_INVALID, "null argument");
   hipSetDevice(c->device);
   const EvalConst C = c->eval_const(b);
   if (ptrs_on_device) {
     const int t0 = c->timing_begin(2);
-    HIP_TRY(c, launch_local_search(C, b->cap, n, lig_idx, genotypes, energy, iters, p->rho, p->eps, c->stream));
+    HIP_TRY(c, launch_local_search(C, cap, n, lig_idx, genotypes, energy, iters, p->rho, p->eps, c->stream));
     c->timing_end(2, t0);
     return AD_OK;
   }
-  for (int q = 0; q < n; ++q)
-    if (lig_idx[q] < 0 || lig_idx[q] >= b->n_lig) return c->fail(AD_E_INVALID, "lig_idx out of range");
+  rc = check_shape_poses(c, b, n, lig_idx, shape);
+  if (rc) return rc;
   const size_t nb_idx = ((size_t)n * 4 + 255) & ~(size_t)255;
   const size_t nb_geo = ((size_t)n * kStride * 4 + 255) & ~(size_t)255;
   char *blk = (char *)c->scratch_alloc(nb_idx + nb_geo + nb_idx, 0);
@@ -626,7 +722,7 @@ extern "C" int ad_local_search(ad_ctx *c, const ad_batch *b, int n, const int *l
   HIP_TRY(c, hipMemcpyAsync(d_idx, lig_idx, (size_t)n * 4, hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipMemcpyAsync(d_geo, genotypes, (size_t)n * kStride * 4, hipMemcpyHostToDevice, c->stream));
   const int t0 = c->timing_begin(2);
-  HIP_TRY(c, launch_local_search(C, b->cap, n, d_idx, d_geo, d_e, iters, p->rho, p->eps, c->stream));
+  HIP_TRY(c, launch_local_search(C, cap, n, d_idx, d_geo, d_e, iters, p->rho, p->eps, c->stream));
   c->timing_end(2, t0);
   HIP_TRY(c, hipMemcpyAsync(genotypes, d_geo, (size_t)n * kStride * 4, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipMemcpyAsync(energy, d_e, (size_t)n * 4, hipMemcpyDeviceToHost, c->stream));

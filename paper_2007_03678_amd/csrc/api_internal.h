@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 
 #include <map>
+#include <mutex>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -108,6 +110,12 @@ struct ad_batch {
 
 struct ad_ctx {
   static constexpr int kScratchSlots = 4;
+  // live children (batches, pre-screens): ad_destroy releases their device
+  // memory and detaches them, so they may be freed after the context in any
+  // order (the free then only deletes the handle)
+  std::mutex child_mu;
+  std::set<ad_batch *> batches;
+  std::set<ad_prescreen *> prescreens;
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
@@ -168,6 +176,15 @@ struct ad_ctx {
     dock_bytes = 0;
   }
 };
+
+// Child registry of a context (api.cpp): register / unregister under the
+// context's lock; batch_release frees a batch's device memory (idempotent).
+void register_batch(ad_ctx *c, ad_batch *b);
+void unregister_batch(ad_ctx *c, ad_batch *b);
+void batch_release(ad_batch *b);
+// pre-screen counterparts (prescreen.hip)
+void register_prescreen(ad_ctx *c, ad_prescreen *ps);
+void prescreen_release(ad_prescreen *ps);
 
 // Ligand loading without the context's error state (api.cpp): the host
 // preparation and upload of ad_load_ligands, and the ligand views of the

@@ -737,6 +737,95 @@ __global__ __launch_bounds__(64) void k_local_search(EvalConst C, int n, const i
 }
 
 // ---------------------------------------------------------------------------
+// Packed evaluation (ad_score_poses_shape / ad_local_search_shape with
+// AD_SHAPE_PACKED): poses 2w and 2w + 1 of one ligand (at most kDualAtoms
+// atoms and kDualTor torsions) on work-group w, one per 32-lane half, through
+// the same evaluate / adadelta_wave instantiation as the packed local search
+// of the docking kernel.  A half whose pose is past n recomputes the last
+// pose and writes nothing; a half whose pose names another ligand than pose
+// 2w writes NaN.
+// ---------------------------------------------------------------------------
+struct DualPose {
+  int half, lane, p, li;
+  bool write, ok;
+};
+
+__device__ __forceinline__ DualPose dual_pose(const EvalConst &C, int n, const int *lig_idx) {
+  DualPose d;
+  d.half = threadIdx.x >> 5;
+  d.lane = threadIdx.x & 31;
+  const int p0 = 2 * (int)blockIdx.x;
+  d.write = p0 + d.half < n;
+  d.p = min(p0 + d.half, n - 1);
+  d.li = lig_idx[p0];   // uniform over the work-group
+  const bool lig_ok = d.li >= 0 && d.li < C.batch.n_lig && C.batch.lig[d.li].n_atoms <= kDualAtoms &&
+                      C.batch.lig[d.li].n_tor <= kDualTor;
+  d.ok = lig_ok && lig_idx[d.p] == d.li;
+  if (!lig_ok) d.li = -1;
+  return d;
+}
+
+template <bool GRAD>
+__global__ __launch_bounds__(64) void k_score_dual(EvalConst C, int n, const int *__restrict__ lig_idx,
+                                                   const float *__restrict__ geno, float *__restrict__ E_out,
+                                                   float *__restrict__ G_out, float *__restrict__ T_out) {
+  __shared__ EvalLds<kDualAtoms, kDualTor> S2[2];
+  const DualPose d = dual_pose(C, n, lig_idx);
+  const int lane = d.lane, half = d.half;
+  EvalLds<kDualAtoms, kDualTor> &S = S2[half];
+  init_eval_lds(S, lane);
+  const float nanf = __builtin_nanf("");
+  if (d.li < 0) {   // no valid ligand for the work-group (device-side indices only)
+    if (d.write) {
+      if (lane == 0) E_out[d.p] = nanf;
+      if (GRAD && G_out) {
+        G_out[(size_t)d.p * kStride + lane] = nanf;
+        if (lane < kStride - 32) G_out[(size_t)d.p * kStride + 32 + lane] = nanf;
+      }
+      if (T_out && lane < 3) T_out[(size_t)d.p * 3 + lane] = nanf;
+    }
+    return;
+  }
+  LaneLig<kDualAtoms> LL;
+  LL.load(C, d.li, lane);
+  S.geno[lane] = (double)geno[(size_t)d.p * kStride + lane];   // 32 slots: 7 + at most 25 torsions
+  __syncthreads();
+  double inter, intra;
+  const double E = evaluate<kDualAtoms, GRAD, false, 32, kDualTor>(C, LL, S, lane, &inter, &intra,
+                                                                   PairStage{0, 0}, half);
+  if (!d.write) return;
+  const bool fin = d.ok && genotype_finite(S.geno, LL.L.n_tor);
+  if (lane == 0) E_out[d.p] = fin ? (float)E : nanf;
+  if (T_out && lane < 3) {
+    const double tv = lane == 0 ? inter : (lane == 1 ? intra : inter + (double)C.ff.w_tor * LL.L.n_tor);
+    T_out[(size_t)d.p * 3 + lane] = fin ? (float)tv : nanf;
+  }
+  if (GRAD) {
+    const double gv = (lane == 6 || lane >= 7 + LL.L.n_tor) ? 0.0 : S.grad[lane];
+    G_out[(size_t)d.p * kStride + lane] = fin ? (float)gv : nanf;
+    if (lane < kStride - 32) G_out[(size_t)d.p * kStride + 32 + lane] = fin ? 0.0f : nanf;
+  }
+}
+
+__global__ __launch_bounds__(64) void k_local_search_dual(EvalConst C, int n, const int *__restrict__ lig_idx,
+                                                          float *__restrict__ geno, float *__restrict__ E, int iters,
+                                                          double rho, double eps) {
+  __shared__ EvalLds<kDualAtoms, kDualTor> S2[2];
+  const DualPose d = dual_pose(C, n, lig_idx);
+  EvalLds<kDualAtoms, kDualTor> &S = S2[d.half];
+  init_eval_lds(S, d.lane);
+  if (d.li < 0) {
+    if (d.write && d.lane == 0) E[d.p] = __builtin_nanf("");
+    return;
+  }
+  LaneLig<kDualAtoms> LL;
+  LL.load(C, d.li, d.lane);
+  adadelta_wave<kDualAtoms, false, 32, kDualTor>(C, LL, S, d.lane, geno + (size_t)d.p * kStride, E + d.p, iters, rho,
+                                                 eps, PairStage{0, 0}, d.half, d.write && d.ok);
+  if (d.write && !d.ok && d.lane == 0) E[d.p] = __builtin_nanf("");
+}
+
+// ---------------------------------------------------------------------------
 // Lamarckian GA on the GPU.  Population state per run R (ligand * nrun +
 // run): genotypes [2][n_runs][pop][40] (ping-pong by generation parity) and
 // energies [2][n_runs][pop].  Every genotype stored is exactly the one that
@@ -1347,7 +1436,11 @@ hipError_t launch_score(const EvalConst &C, int cap, int n, const int *lig_idx, 
                         float *T, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   dim3 grid(n), block(64);
-  if (cap <= 64) {
+  if (cap <= 32) {   // packed: two poses per wavefront
+    const dim3 g2((n + 1) / 2);
+    if (G) hipLaunchKernelGGL((k_score_dual<true>), g2, block, 0, s, C, n, lig_idx, geno, E, G, T);
+    else hipLaunchKernelGGL((k_score_dual<false>), g2, block, 0, s, C, n, lig_idx, geno, E, G, T);
+  } else if (cap <= 64) {
     if (G) hipLaunchKernelGGL((k_score<64, true>), grid, block, 0, s, C, n, lig_idx, geno, E, G, T);
     else hipLaunchKernelGGL((k_score<64, false>), grid, block, 0, s, C, n, lig_idx, geno, E, G, T);
   } else {
@@ -1361,8 +1454,13 @@ hipError_t launch_local_search(const EvalConst &C, int cap, int n, const int *li
                                int iters, double rho, double eps, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   dim3 grid(n), block(64);
-  if (cap <= 64) hipLaunchKernelGGL((k_local_search<64>), grid, block, 0, s, C, n, lig_idx, geno, E, iters, rho, eps);
-  else hipLaunchKernelGGL((k_local_search<128>), grid, block, 0, s, C, n, lig_idx, geno, E, iters, rho, eps);
+  if (cap <= 32) {
+    hipLaunchKernelGGL(k_local_search_dual, dim3((n + 1) / 2), block, 0, s, C, n, lig_idx, geno, E, iters, rho, eps);
+  } else if (cap <= 64) {
+    hipLaunchKernelGGL((k_local_search<64>), grid, block, 0, s, C, n, lig_idx, geno, E, iters, rho, eps);
+  } else {
+    hipLaunchKernelGGL((k_local_search<128>), grid, block, 0, s, C, n, lig_idx, geno, E, iters, rho, eps);
+  }
   return hipGetLastError();
 }
 

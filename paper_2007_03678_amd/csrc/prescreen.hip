@@ -809,7 +809,7 @@ int step_grad(ad_prescreen *ps, const ad_batch *b, MB &mb) {
 }
 
 int check_ps(ad_prescreen *ps, const ad_batch *b, int n, const int *idx) {
-  if (!ps) return AD_E_INVALID;
+  if (!ps || !ps->ctx) return AD_E_INVALID;   // null, or detached by ad_destroy
   ad_ctx *c = ps->ctx;
   if (!b || b->ctx != c) return c->fail(AD_E_INVALID, "bad batch");
   if (!b->ps_ok) return c->fail(AD_E_INVALID, "batch has atoms with more than 8 bonds (pre-screen limit)");
@@ -870,28 +870,47 @@ extern "C" int ad_prescreen_create(ad_ctx *c, const ad_prescreen_cfg *cfg, uint6
     ad_prescreen_destroy(ps);
     return rc;
   }
+  register_prescreen(c, ps);
   *out = ps;
   return AD_OK;
 }
 
-extern "C" void ad_prescreen_destroy(ad_prescreen *ps) {
-  if (!ps) return;
+void register_prescreen(ad_ctx *c, ad_prescreen *ps) {
+  std::lock_guard<std::mutex> lk(c->child_mu);
+  c->prescreens.insert(ps);
+}
+
+// Frees the pre-screen's device memory and detaches it from its context
+// (called by ad_destroy for pre-screens still alive, under the context lock).
+void prescreen_release(ad_prescreen *ps) {
+  if (!ps->ctx) return;
   hipSetDevice(ps->ctx->device);
   hipStreamSynchronize(ps->ctx->stream);
-  hipFree(ps->w);
-  hipFree(ps->gr);
-  hipFree(ps->m);
-  hipFree(ps->v);
-  hipFree(ps->wbf);
-  hipFree(ps->work);
-  hipFree(ps->plan);
+  void *bufs[] = {ps->w, ps->gr, ps->m, ps->v, ps->wbf, ps->work, ps->plan};
+  for (void *p : bufs)
+    if (p) hipFree(p);
+  ps->w = ps->gr = ps->m = ps->v = nullptr;
+  ps->wbf = nullptr;
+  ps->work = ps->plan = nullptr;
+  ps->work_bytes = ps->plan_bytes = 0;
+  ps->ctx = nullptr;
+}
+
+extern "C" void ad_prescreen_destroy(ad_prescreen *ps) {
+  if (!ps) return;
+  if (ps->ctx) {
+    ad_ctx *c = ps->ctx;
+    std::lock_guard<std::mutex> lk(c->child_mu);
+    c->prescreens.erase(ps);
+    prescreen_release(ps);
+  }
   delete ps;
 }
 
 extern "C" int ad_prescreen_n_params(void) { return (int)make_offs().total; }
 
 extern "C" int ad_prescreen_set_params(ad_prescreen *ps, const float *params) {
-  if (!ps || !params) return AD_E_INVALID;
+  if (!ps || !ps->ctx || !params) return AD_E_INVALID;
   ad_ctx *c = ps->ctx;
   const size_t P = ps->o.total;
   for (size_t i = 0; i < P; ++i)
@@ -908,7 +927,7 @@ extern "C" int ad_prescreen_set_params(ad_prescreen *ps, const float *params) {
 }
 
 extern "C" int ad_prescreen_get_params(ad_prescreen *ps, float *params) {
-  if (!ps || !params) return AD_E_INVALID;
+  if (!ps || !ps->ctx || !params) return AD_E_INVALID;
   ad_ctx *c = ps->ctx;
   hipSetDevice(c->device);
   PS_TRY(c, hipMemcpyAsync(params, ps->w, ps->o.total * 4, hipMemcpyDeviceToHost, c->stream));

@@ -119,3 +119,17 @@ def test_oracle_and_product_accept_the_same_ligands(pkg, orc):
         except ValueError:
             ok = False
         assert (rc == 0) == ok
+
+
+def test_grid_check_rejects_index_overflow(pkg):
+    # the kernels multiply (map * nz + k) by nx * ny in 24-bit products
+    ok = synth.Grid((40, 40, 40), 0.375, (0.0, 0.0, 0.0), list(range(8)))
+    assert pkg.ad_grid_check(ok, 8) == (0, "")
+    thin = synth.Grid((2, 2, 1 << 22), 0.375, (0.0, 0.0, 0.0), list(range(8)))   # 8 * 2^22 = 2^25 rows
+    rc, msg = pkg.ad_grid_check(thin, 8)
+    assert rc == pkg.AD_E_INVALID and "n_maps*nz" in msg
+    wide = synth.Grid((4096, 4096, 2), 0.375, (0.0, 0.0, 0.0), [0])   # nx * ny = 2^24
+    assert pkg.ad_grid_check(wide, 8)[0] == pkg.AD_E_INVALID
+    for bad in (synth.Grid((1, 40, 40), 0.375, (0, 0, 0), [0]), synth.Grid((40, 40, 40), 0.0, (0, 0, 0), [0]),
+                synth.Grid((40, 40, 40), 0.375, (0, 0, 0), [0, 0]), synth.Grid((40, 40, 40), 0.375, (0, 0, 0), [9])):
+        assert pkg.ad_grid_check(bad, 8)[0] == pkg.AD_E_INVALID
