@@ -14,15 +14,22 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
+COUNT_LIB_PATH = os.path.join(HERE, "liboracle_opcount.so")
 MAXT, MAXA, MAXTOR, STRIDE = 16, 128, 32, 40
 
 
 def build(verbose: bool = False) -> str:
-    """Compile liboracle.so (always recompiles)."""
+    """Compile liboracle.so and its op-counting build liboracle_opcount.so
+    (oracle.c compiled as C++ with a counting double, opcount.hpp); always
+    recompiles."""
     cmd = ["gcc", "-O3", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wno-unused-parameter",
            os.path.join(HERE, "oracle.c"), "-o", LIB_PATH + ".tmp", "-lm"]
     subprocess.run(cmd, check=True, capture_output=not verbose)
     os.replace(LIB_PATH + ".tmp", LIB_PATH)
+    cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-fPIC", "-shared", "-I", HERE,
+           os.path.join(HERE, "opcount.cpp"), "-o", COUNT_LIB_PATH + ".tmp", "-lm"]
+    subprocess.run(cmd, check=True, capture_output=not verbose)
+    os.replace(COUNT_LIB_PATH + ".tmp", COUNT_LIB_PATH)
     return LIB_PATH
 
 
@@ -76,15 +83,17 @@ def make_params(**kw) -> DockParams:
     return p
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(LIB_PATH):
+def lib(counting: bool = False):
+    """The oracle library; counting=True: its op-counting build (same C ABI
+    plus orc_opcount_reset / orc_opcount_get)."""
+    if counting not in _libs:
+        path = COUNT_LIB_PATH if counting else LIB_PATH
+        if not os.path.exists(path):
             build()
-        L = C.CDLL(LIB_PATH)
+        L = C.CDLL(path)
         vp, ip, dp, fp = C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_double), C.POINTER(C.c_float)
         u32 = C.c_uint32
         L.orc_philox4x32_10.argtypes = [C.POINTER(u32), C.POINTER(u32), C.POINTER(u32)]
@@ -136,8 +145,13 @@ def lib():
                                    C.POINTER(C.c_int64), ip]
         L.orc_dock.argtypes = [vp, vp, C.POINTER(DockParams), C.c_uint64, u32, dp, dp,
                                C.POINTER(C.c_int64), ip, C.c_int]
-        _lib = L
-    return _lib
+        if counting:
+            L.orc_opcount_reset.argtypes = []
+            L.orc_opcount_reset.restype = None
+            L.orc_opcount_get.argtypes = [C.POINTER(C.c_uint64)]
+            L.orc_opcount_get.restype = None
+        _libs[counting] = L
+    return _libs[counting]
 
 
 def _p(a, ct):
@@ -162,10 +176,24 @@ def _f64(a):
 class Oracle:
     """Thin object holding the force field; all methods call the C oracle."""
 
-    def __init__(self, ff: dict):
+    def __init__(self, ff: dict, counting: bool = False):
         self.ff_dict = ff
         self.ff = make_ff(ff)
-        self.L = lib()
+        self.L = lib(counting)
+        self.counting = counting
+
+    def opcount(self, fn, *args, **kw):
+        """(fn's result, floating-point operations it ran) with the op-counting
+        build: {add, mul, div, func, total}; add counts subtractions, func the
+        transcendentals (each one operation)."""
+        assert self.counting, "needs Oracle(ff, counting=True)"
+        self.L.orc_opcount_reset()
+        out = fn(*args, **kw)
+        c = (C.c_uint64 * 4)()
+        self.L.orc_opcount_get(c)
+        d = dict(add=int(c[0]), mul=int(c[1]), div=int(c[2]), func=int(c[3]))
+        d["total"] = sum(d.values())
+        return out, d
 
     # pair terms -----------------------------------------------------------
     def lj(self, ti, tj, r):
