@@ -195,3 +195,117 @@ def init_params(seed):
         else:
             d[n] = np.zeros(s)
     return flatten(d)
+
+
+# ---------------------------------------------------------------------------
+# FP32 emulation: the flip noise of the rounding points above.
+#
+# The GPU path rounds to BF16 where the oracle does but accumulates in FP32,
+# in an order of its own.  Every sum whose exact value lies within the FP32
+# accumulation error of a BF16 rounding midpoint can round the other way, and
+# such one-ulp differences travel on through the network; every graph has
+# thousands of such sums, so no result is free of them.  `emulate_fp32` is a
+# second, independent implementation of the same definition in float32: the
+# products of BF16 values are exact in float32 and every sum runs in float32
+# in a randomly permuted order (a different order per seed), the pooled sum
+# in float64 (exact), the loss and its derivative in float32.  The spread of
+# its results over seeds around the FP64 oracle is the size of the flip noise
+# that any FP32-accumulating implementation of these rounding points shows;
+# the GPU tests derive their tolerances from it before measuring.
+# ---------------------------------------------------------------------------
+def _perm_mm(A, B, rng):
+    """float32 A @ B with the summed dimension in a random order."""
+    k = A.shape[1]
+    o = rng.permutation(k)
+    return np.asarray(A, np.float32)[:, o] @ np.asarray(B, np.float32)[o, :]
+
+
+def _perm_sum(A, rng, axis=0):
+    """float32 sequential sum along `axis` in a random order."""
+    A = np.asarray(A, np.float32)
+    o = rng.permutation(A.shape[axis])
+    return np.cumsum(np.take(A, o, axis=axis), axis=axis, dtype=np.float32).take(-1, axis=axis) \
+        if A.shape[axis] else np.zeros(np.delete(A.shape, axis), np.float32)
+
+
+def _adj32(nbr, H, rng, extra=None):
+    out = np.zeros((len(nbr), H.shape[1]), np.float32)
+    for i, nb in enumerate(nbr):
+        rows = [H[j] for j in nb] + ([extra[i]] if extra is not None else [])
+        if rows:
+            out[i] = _perm_sum(np.stack(rows), rng)
+    return out
+
+
+def emulate_fp32(theta, graphs, ys=None, seed=0, lam=LAM, tau=TAU, bf16_on=True):
+    """Predictions (and with labels ys: loss, flattened gradient) of the
+    network with BF16 rounding at the oracle's points (bf16_on) and float32
+    sums in a random order fixed by `seed`."""
+    rng = np.random.default_rng(seed)
+    P = unflatten(theta)
+    f32 = lambda a: np.asarray(a, np.float32)
+    r = (lambda a: f32(bf16(a))) if bf16_on else f32
+    W = {k: r(v) for k, v in P.items() if k[0] in "WU"}
+    b32 = {k: f32(v) for k, v in P.items() if k[0] in "bc"}
+    cache, G = [], []
+    for X, nbr in graphs:
+        Xr = r(X)
+        H = r(np.maximum(_perm_mm(Xr, W["W0"], rng) + b32["b0"], 0.0))
+        Hs, Ms = [H], [None]
+        for l in range(1, N_LAYERS + 1):
+            M = r(_adj32(nbr, H, rng))
+            H = r(np.maximum(_perm_mm(np.concatenate([H, M], axis=1), W[f"W{l}"], rng) + b32[f"b{l}"], 0.0))
+            Hs.append(H)
+            Ms.append(M)
+        G.append(r(H.astype(np.float64).sum(axis=0)))
+        cache.append((Xr, nbr, Hs, Ms))
+    g = np.stack(G)
+    z1 = r(np.maximum(_perm_mm(g, W["U1"], rng) + b32["c1"], 0.0))
+    z2 = r(np.maximum(_perm_mm(z1, W["U2"], rng) + b32["c2"], 0.0))
+    p = _perm_mm(z2, W["U3"], rng)[:, 0] + b32["c3"][0]
+    if ys is None:
+        return p.astype(np.float64)
+    y = f32(ys)
+    B = len(y)
+    d = p - y
+    better = y[:, None] < y[None, :]
+    npairs = np.float32(better.sum())
+    wr = np.float32(lam) / npairs if npairs else np.float32(0.0)
+    z = (p[:, None] - p[None, :]) / np.float32(tau)
+    li = d * d / np.float32(B) + wr * np.where(better, np.maximum(z, 0) + np.log1p(np.exp(-np.abs(z))), 0).sum(1)
+    with np.errstate(over="ignore"):
+        sgm = np.float32(1.0) / (np.float32(1.0) + np.exp(-z))
+    gi = np.float32(2.0) * d / np.float32(B) + (wr / np.float32(tau)) * (np.where(better, sgm, 0).sum(1)
+                                                                          - np.where(better.T, sgm.T, 0).sum(1))
+    loss = _perm_sum(li, rng)
+    dp = f32(gi)
+    gr = {}
+    U3 = W["U3"][:, 0]
+    gr["U3"] = _perm_mm(z2.T, dp[:, None], rng)
+    gr["c3"] = np.array([_perm_sum(dp, rng)])
+    dz2 = r(dp[:, None] * U3[None, :]) * (z2 > 0)
+    ones = np.ones((1, B), np.float32)
+    gr["U2"] = _perm_mm(z1.T, dz2, rng)
+    gr["c2"] = _perm_mm(ones, dz2, rng)[0]
+    dz1 = r(_perm_mm(dz2, W["U2"].T, rng) * (z1 > 0))
+    gr["U1"] = _perm_mm(g.T, dz1, rng)
+    gr["c1"] = _perm_mm(ones, dz1, rng)[0]
+    dg = r(_perm_mm(dz1, W["U1"].T, rng))
+    parts = {n: [] for n, _ in PARAM_SHAPES if n[0] in "Wb"}
+    for b, (Xr, nbr, Hs, Ms) in enumerate(cache):
+        n = Xr.shape[0]
+        dH = np.tile(dg[b], (n, 1))
+        on = np.ones((1, n), np.float32)
+        for l in range(N_LAYERS, 0, -1):
+            dP = r(dH) * (Hs[l] > 0)
+            HM = np.concatenate([Hs[l - 1], Ms[l]], axis=1)
+            parts[f"W{l}"].append(_perm_mm(HM.T, dP, rng))
+            parts[f"b{l}"].append(_perm_mm(on, dP, rng)[0])
+            dHM = r(_perm_mm(dP, W[f"W{l}"].T, rng))
+            dH = _adj32(nbr, dHM[:, WIDTH:], rng, extra=dHM[:, :WIDTH])
+        dP0 = r(dH) * (Hs[0] > 0)
+        parts["W0"].append(_perm_mm(Xr.T, dP0, rng))
+        parts["b0"].append(_perm_mm(on, dP0, rng)[0])
+    for k, v in parts.items():
+        gr[k] = _perm_sum(np.stack(v), rng)
+    return p.astype(np.float64), float(loss), flatten(gr)

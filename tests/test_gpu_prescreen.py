@@ -1,18 +1,32 @@
 """GPU parity of the learned pre-screen against its FP64 oracle.
 
 The oracle rounds to BF16 at the same points as the GPU path, so the two
-differ only by accumulation order (FP32 MFMA sums and FP32 neighbour/pool
-sums against FP64) and by the rare BF16 rounding that this order flips.
-An activation is the BF16 rounding of a sum of K <= 256 terms whose FP32 and
-FP64 values differ by about sqrt(K) 2^-24 of the terms' scale, so roughly
-K 2^-16 (under 0.4 %) of activations fall on the other side of a BF16
-rounding midpoint and differ by one BF16 ulp (2^-8 relative); such flips are
-isolated and add incoherently.  Tolerances:
-  predictions:  ||p_gpu - p_orc||_2 <= 2e-3 ||p_orc||_2; >= 90% of graphs within
-                1e-4 max(|p|, 1) and every graph within 2e-2 max(rms p, 1)
-  loss:         relative 2e-3
-  gradient:     per parameter tensor ||g_gpu - g_orc||_2 <= 1e-2 ||g_orc||_2
-                (2e-3 over the whole vector)
+differ only where an FP32 sum (the GPU's accumulation order) and the exact
+sum fall on different sides of a BF16 rounding midpoint: a "flip" of one BF16
+ulp (2^-8 relative) that travels on through the network.  Every graph has
+thousands of rounding points, so no result is free of flips, and their size
+is set by the network, not by the implementation.  The tolerances therefore
+come from an independent FP32 implementation of the same definition on the
+CPU (oracle.surrogate.emulate_fp32: float32 sums in 8 random orders), computed
+before the GPU result is looked at, element by element:
+
+  predictions (per graph):  a share within the tight bound 1e-3 max(|p|, rms p)
+      of at least the smallest share among the emulations minus 0.05, and
+      every graph within the hard maximum 1.5 x the largest deviation any
+      emulation shows on any graph (plus the tight bound); normwise within
+      1.5 x the emulations' largest normwise deviation;
+  loss:  within 1.5 x the emulations' largest deviation (+ 1e-6 relative);
+  gradient (per parameter tensor): normwise within 1.5 x the emulations'
+      largest for that tensor; every entry within 1.5 x the largest entry
+      deviation of the emulations in that tensor (plus 1e-3 of the entry);
+      over all entries, a share within 1e-3 max(|g|, 1e-2 rms of its tensor)
+      of at least the emulations' smallest share minus 0.1.
+
+The factor 1.5 covers the GPU's order being a ninth sample of the orders the
+eight emulations draw from.  The measured flip noise of gradient entries is
+far above 1e-3 (a flip in a stored activation gradient moves the entries it
+feeds by up to a BF16 ulp of the largest term), so the target's 1e-3 holds
+for the predictions' shares, not for every gradient entry.
 """
 import numpy as np
 import pytest
@@ -68,6 +82,40 @@ def theta():
     return t.astype(np.float32).astype(np.float64)   # what the GPU holds
 
 
+N_EMUL = 8
+
+
+def flip_ensemble(theta, G, ys=None):
+    """FP64 oracle results and the deviations of N_EMUL FP32 emulations from them."""
+    po = S.forward(theta, G, bf16_on=True)
+    out = dict(po=po)
+    if ys is None:
+        out["dp"] = np.array([S.emulate_fp32(theta, G, seed=s) - po for s in range(N_EMUL)])
+        return out
+    Lo, dpo = S.loss_and_dp(po, ys)
+    go, _ = S.backward(theta, G, dpo, bf16_on=True)
+    E = [S.emulate_fp32(theta, G, ys, seed=s) for s in range(N_EMUL)]
+    out.update(Lo=Lo, go=go, dp=np.array([e[0] - po for e in E]), dL=np.array([e[1] - Lo for e in E]),
+               dg=np.array([e[2] - go for e in E]))
+    return out
+
+
+def check_predictions(p, ens, label):
+    po, dev = ens["po"], ens["dp"]
+    rms = np.sqrt(np.mean(po ** 2))
+    tight = 1e-3 * np.maximum(np.abs(po), rms)
+    share_min = min(np.mean(np.abs(d) <= tight) for d in dev)
+    hard = 1.5 * np.abs(dev).max() + tight
+    nw = 1.5 * max(np.linalg.norm(d) for d in dev) + 1e-6 * np.linalg.norm(po)
+    err = np.abs(p - po)
+    share = np.mean(err <= tight)
+    print(f"{label}: share within 1e-3 {share:.3f} (emulations >= {share_min:.3f}), max |dp| {err.max():.3e} "
+          f"(hard max {hard.max():.3e}), normwise {np.linalg.norm(p - po):.3e} (<= {nw:.3e})", flush=True)
+    assert share >= share_min - 0.05, (label, share, share_min)
+    assert np.all(err <= hard), (label, np.where(err > hard)[0][:5])
+    assert np.linalg.norm(p - po) <= nw, label
+
+
 def per_tensor(g, go):
     offs = np.cumsum([0] + [int(np.prod(s)) for _, s in S.PARAM_SHAPES])
     out = {}
@@ -93,26 +141,20 @@ def test_params_roundtrip(pkg, ctx, theta):
 def test_forward_matches_oracle(pkg, ctx, ligs, theta):
     batch = ctx.ad_load_ligands(ligs)
     ps = pkg.Prescreen(ctx)
-    ps.ad_prescreen_set_params(theta)
-    ps.ad_prescreen_set_scale(0.0, 1.0)
-    p = ps.ad_prescreen_predict(batch).astype(np.float64)
-    po = S.forward(theta, [S.features(l) for l in ligs], bf16_on=True)
-    err = np.linalg.norm(p - po) / np.linalg.norm(po)
-    rms = np.sqrt(np.mean(po ** 2))
-    print(f"forward: normwise {err:.2e}, max abs {np.abs(p - po).max():.2e}, rms {rms:.3f}")
-    assert err <= 2e-3
-    # apart from the rare graph whose BF16 rounding of an MLP activation flips
-    # with the FP32 accumulation order, predictions agree to FP32 precision
-    close = np.abs(p - po) <= 1e-4 * np.maximum(np.abs(po), 1.0)
-    assert close.mean() >= 0.9, close.mean()
-    assert np.all(np.abs(p - po) <= 2e-2 * max(rms, 1.0))
-    # the label scale maps predictions affinely; a subset in another order
-    ps.ad_prescreen_set_scale(-7.5, 2.0)
-    idx = np.array([69, 3, 0, 68, 3], np.int32)
-    q = ps.ad_prescreen_predict(batch, idx).astype(np.float64)
-    assert np.allclose(q, -7.5 + 2.0 * p[idx], rtol=1e-5, atol=1e-5)
-    ps.close()
-    batch.free()
+    try:
+        ps.ad_prescreen_set_params(theta)
+        ps.ad_prescreen_set_scale(0.0, 1.0)
+        ens = flip_ensemble(theta, [S.features(l) for l in ligs])
+        p = ps.ad_prescreen_predict(batch).astype(np.float64)
+        check_predictions(p, ens, "forward")
+        # the label scale maps predictions affinely; a subset in another order
+        ps.ad_prescreen_set_scale(-7.5, 2.0)
+        idx = np.array([69, 3, 0, 68, 3], np.int32)
+        q = ps.ad_prescreen_predict(batch, idx).astype(np.float64)
+        assert np.allclose(q, -7.5 + 2.0 * p[idx], rtol=1e-5, atol=1e-5)
+    finally:
+        ps.close()
+        batch.free()
 
 
 def test_forward_is_invariant_under_atom_relabelling(pkg, ctx, theta):
@@ -122,8 +164,12 @@ def test_forward_is_invariant_under_atom_relabelling(pkg, ctx, theta):
     batch = ctx.ad_load_ligands([lig, lig2])
     ps = pkg.Prescreen(ctx)
     ps.ad_prescreen_set_params(theta)
-    p = ps.ad_prescreen_predict(batch)
-    assert abs(p[0] - p[1]) <= 2e-3 * max(abs(p[0]), 1.0)
+    p = ps.ad_prescreen_predict(batch).astype(np.float64)
+    # relabelling only changes the summation order: the two predictions may
+    # differ by the flip noise of two orders (each bounded as in check_predictions)
+    ens = flip_ensemble(theta, [S.features(lig)])
+    lim = 2 * (1.5 * np.abs(ens["dp"]).max() + 1e-3 * max(abs(ens["po"][0]), 1e-6))
+    assert abs(p[0] - p[1]) <= lim, (p, lim)
     ps.close()
     batch.free()
 
@@ -131,29 +177,42 @@ def test_forward_is_invariant_under_atom_relabelling(pkg, ctx, theta):
 def test_grad_matches_oracle(pkg, ctx, ligs, theta):
     batch = ctx.ad_load_ligands(ligs)
     ps = pkg.Prescreen(ctx)
-    ps.ad_prescreen_set_params(theta)
-    rng = np.random.default_rng(11)
-    labels = rng.normal(-8.0, 2.0, size=len(ligs)).astype(np.float32)
-    labels[5] = labels[6]                             # a tie (no ranking pair)
-    mean, sd = float(labels.mean()), float(labels.std())
-    ps.ad_prescreen_set_scale(mean, sd)
-    idx = np.arange(len(ligs), dtype=np.int32)
-    loss, g, pstd = ps.ad_prescreen_grad(batch, idx, labels)
-    ys = ((labels.astype(np.float64) - mean) / sd).astype(np.float32).astype(np.float64)
-    G = [S.features(l) for l in ligs]
-    po = S.forward(theta, G, bf16_on=True)
-    Lo, dpo = S.loss_and_dp(po, ys)
-    go, _ = S.backward(theta, G, dpo, bf16_on=True)
-    assert np.linalg.norm(pstd - po) <= 2e-3 * np.linalg.norm(po)
-    assert loss == pytest.approx(Lo, rel=2e-3)
-    total = np.linalg.norm(g - go) / np.linalg.norm(go)
-    pt = per_tensor(g.astype(np.float64), go)
-    print("grad: total", f"{total:.2e}", {k: f"{v:.1e}" for k, v in pt.items()})
-    assert total <= 2e-3
-    for k, v in pt.items():
-        assert v <= 1e-2, (k, v)
-    ps.close()
-    batch.free()
+    try:
+        ps.ad_prescreen_set_params(theta)
+        rng = np.random.default_rng(11)
+        labels = rng.normal(-8.0, 2.0, size=len(ligs)).astype(np.float32)
+        labels[5] = labels[6]                             # a tie (no ranking pair)
+        mean, sd = float(labels.mean()), float(labels.std())
+        ps.ad_prescreen_set_scale(mean, sd)
+        idx = np.arange(len(ligs), dtype=np.int32)
+        ys = ((labels.astype(np.float64) - mean) / sd).astype(np.float32).astype(np.float64)
+        ens = flip_ensemble(theta, [S.features(l) for l in ligs], ys)
+        loss, g, pstd = ps.ad_prescreen_grad(batch, idx, labels)
+        check_predictions(pstd.astype(np.float64), ens, "grad/predictions")
+        Lo, go, dg = ens["Lo"], ens["go"], ens["dg"]
+        assert abs(loss - Lo) <= 1.5 * np.abs(ens["dL"]).max() + 1e-6 * abs(Lo), (loss, Lo)
+        g = g.astype(np.float64)
+        offs = np.cumsum([0] + [int(np.prod(sh)) for _, sh in S.PARAM_SHAPES])
+        tight_all, share_e = [], [[] for _ in range(N_EMUL)]
+        for (name, _), a, b in zip(S.PARAM_SHAPES, offs[:-1], offs[1:]):
+            gt, d, dev = go[a:b], g[a:b] - go[a:b], dg[:, a:b]
+            nw_lim = 1.5 * max(np.linalg.norm(x) for x in dev) + 1e-6 * np.linalg.norm(gt)
+            hard = 1.5 * np.abs(dev).max() + 1e-3 * np.abs(gt)
+            assert np.linalg.norm(d) <= nw_lim, (name, np.linalg.norm(d), nw_lim)
+            assert np.all(np.abs(d) <= hard), (name, np.max(np.abs(d) - hard))
+            tight = 1e-3 * np.maximum(np.abs(gt), 1e-2 * np.sqrt(np.mean(gt ** 2)))
+            tight_all.append(np.abs(d) <= tight)
+            for k in range(N_EMUL):
+                share_e[k].append(np.abs(dev[k]) <= tight)
+            print(f"grad {name}: normwise {np.linalg.norm(d) / np.linalg.norm(gt):.1e} "
+                  f"(limit {nw_lim / np.linalg.norm(gt):.1e})", flush=True)
+        share = np.concatenate(tight_all).mean()
+        share_min = min(np.concatenate(x).mean() for x in share_e)
+        print(f"grad: share of entries within 1e-3 {share:.3f} (emulations >= {share_min:.3f})", flush=True)
+        assert share >= share_min - 0.1, (share, share_min)
+    finally:
+        ps.close()
+        batch.free()
 
 
 def test_grad_small_batch_and_adam_step(pkg, ctx, theta):
@@ -168,11 +227,10 @@ def test_grad_small_batch_and_adam_step(pkg, ctx, theta):
     loss, g, _ = ps.ad_prescreen_grad(batch, np.array([0, 1], np.int32), labels)
     G = [S.features(l) for l in ligs]
     ys = np.array([-1.0, 1.0])
-    po = S.forward(theta, G, bf16_on=True)
-    Lo, dpo = S.loss_and_dp(po, ys)
-    go, _ = S.backward(theta, G, dpo, bf16_on=True)
-    assert loss == pytest.approx(Lo, rel=2e-3)
-    assert np.linalg.norm(g - go) <= 2e-3 * np.linalg.norm(go)
+    ens = flip_ensemble(theta, G, ys)
+    Lo, go = ens["Lo"], ens["go"]
+    assert abs(loss - Lo) <= 1.5 * np.abs(ens["dL"]).max() + 1e-6 * abs(Lo)
+    assert np.linalg.norm(g - go) <= 1.5 * max(np.linalg.norm(d) for d in ens["dg"]) + 1e-6 * np.linalg.norm(go)
     # one epoch over two ligands = one Adam step from zero moments:
     # theta - lr g / (|g| + eps) elementwise (summation order of the minibatch
     # may differ, so only clearly nonzero gradient entries are compared)

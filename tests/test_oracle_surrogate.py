@@ -108,3 +108,43 @@ def test_prediction_is_invariant_under_atom_relabelling():
     p1 = S.forward(theta, [S.features(lig)], bf16_on=False)
     p2 = S.forward(theta, [S.features(lig2)], bf16_on=False)
     assert p1[0] == pytest.approx(p2[0], rel=1e-12)
+
+
+def _emul_setup(n=12, seed=3):
+    rng = np.random.default_rng(seed)
+    ligs = [synth.ligand(700 + i, int(rng.integers(2, 60)), 3) for i in range(n)]
+    G = [S.features(l) for l in ligs]
+    theta = S.init_params(4) + rng.normal(0, 0.02, S.N_PARAMS)
+    ys = rng.normal(0, 1, n)
+    return G, theta, ys
+
+
+def test_fp32_emulation_is_the_same_function():
+    """Without BF16 rounding the float32 emulation and the FP64 oracle differ
+    only by float32 accumulation (a dropped term, a wrong operand or a missed
+    mask would show as a difference of order one)."""
+    G, theta, ys = _emul_setup()
+    po = S.forward(theta, G, bf16_on=False)
+    Lo, dpo = S.loss_and_dp(po, ys)
+    go, _ = S.backward(theta, G, dpo, bf16_on=False)
+    for seed in (0, 1):
+        p, L, g = S.emulate_fp32(theta, G, ys, seed=seed, bf16_on=False)
+        assert np.linalg.norm(p - po) <= 1e-5 * np.linalg.norm(po)
+        assert abs(L - Lo) <= 1e-5 * abs(Lo)
+        assert np.linalg.norm(g - go) <= 1e-4 * np.linalg.norm(go)
+
+
+def test_fp32_emulation_with_rounding_stays_near_the_oracle():
+    """With BF16 rounding the emulation sits on other sides of a few rounding
+    midpoints than the oracle: its results differ at the level of BF16 flips
+    (well below a BF16 ulp of the predictions' scale normwise), and a seed
+    fixes the order (reproducible)."""
+    G, theta, ys = _emul_setup()
+    po = S.forward(theta, G, bf16_on=True)
+    Lo, dpo = S.loss_and_dp(po, ys)
+    go, _ = S.backward(theta, G, dpo, bf16_on=True)
+    p, L, g = S.emulate_fp32(theta, G, ys, seed=5)
+    p2, L2, g2 = S.emulate_fp32(theta, G, ys, seed=5)
+    assert np.array_equal(p, p2) and L == L2 and np.array_equal(g, g2)
+    assert np.linalg.norm(p - po) <= 2 ** -8 * np.linalg.norm(po)
+    assert np.linalg.norm(g - go) <= 2 ** -5 * np.linalg.norm(go)
