@@ -290,10 +290,11 @@ class Batch:
             lib().ad_free_batch(self.h)
             self.h = None
 
-    def __del__(self):
-        # at interpreter shutdown the HIP runtime may already be gone: the
-        # process is ending and the driver reclaims the memory
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # at interpreter shutdown the HIP runtime may already be gone (and
+        # module globals cleared): the process is ending, the driver reclaims
+        # the memory
+        if _finalizing():
             return
         try:
             self.free()
@@ -542,8 +543,8 @@ class Context:
             lib().ad_destroy(self.h)
             self.h = None
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():
             return
         try:
             self.close()
@@ -621,8 +622,8 @@ class Prescreen:
             lib().ad_prescreen_destroy(self.h)
             self.h = None
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():
             return
         try:
             self.close()

@@ -22,6 +22,7 @@ import pytest
 
 import binding_poses as bp
 import oracle
+import synth
 
 pytestmark = pytest.mark.gpu
 
@@ -136,7 +137,15 @@ def test_packed_and_wave64_local_search_follow_oracle(pkg, ctx, orc):
 def test_shape_validation(pkg, ctx, orc):
     grid, G, c, s = bp.site(orc, "pocket")
     ctx.ad_load_grids(grid, G.values())
-    ligs = bp.ligands([(20, 4), (40, 8), (30, 26)], 300)
+    # a zigzag chain of 30 atoms with 26 rotatable bonds: over the packed torsion limit
+    x = np.zeros((30, 3), np.float32)
+    x[:, 0] = 1.26 * np.arange(30)
+    x[1::2, 1] = 0.8
+    chain = synth.Ligand(np.zeros(30, np.int32), np.zeros(30, np.float32), x,
+                         np.array([[i, i + 1] for i in range(29)], np.int32),
+                         np.array([0] + [1] * 26 + [0, 0], np.uint8))
+    ligs = bp.ligands([(20, 4), (40, 8)], 300) + [chain]
+    assert chain.n_torsions == 26
     batch = ctx.ad_load_ligands(ligs)
     try:
         g = np.zeros((2, 40), np.float32)

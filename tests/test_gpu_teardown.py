@@ -71,5 +71,6 @@ def test_teardown_in_any_order_exits_cleanly():
                        timeout=300)
     print(r.stdout[-2000:], r.stderr[-2000:], flush=True)
     assert r.returncode == 0, (r.returncode, r.stderr[-2000:])
+    assert "Exception ignored" not in r.stderr, r.stderr[-2000:]
     for tag in ("detached ok", "cycles ok", "exit"):
         assert tag in r.stdout

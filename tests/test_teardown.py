@@ -94,3 +94,4 @@ def test_exit_with_live_cycle(stub):
     """)
     assert r.returncode == 0, r.stderr
     assert "live 0" in r.stdout, r.stdout
+    assert "Exception ignored" not in r.stderr, r.stderr
