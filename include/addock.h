@@ -218,6 +218,24 @@ int ad_score_poses(ad_ctx *ctx, const ad_batch *b, int n, const int *lig_idx, co
 int ad_score_poses_shape(ad_ctx *ctx, const ad_batch *b, int n, const int *lig_idx, const float *genotypes,
                          float *energy, float *grad, float *terms, int ptrs_on_device, int shape);
 
+/* ad_score_poses_noalloc: for callers that cannot allocate device memory
+ * during the call (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Computes exactly what ad_score_poses
+ * computes with host buffers (ptrs_on_device = 0; same kernels, bitwise the
+ * same results) but stages indices, genotypes and results through a static
+ * device block of AD_NOALLOC_MAX_POSES poses (1.33 MiB) that every GPU the
+ * library runs on holds until the process ends, so the call allocates
+ * nothing.  lig_idx, genotypes, energy, grad (optional, [n][40]) and terms
+ * (optional, [n][3]) are host pointers; the call returns when the results
+ * are in them.  Every section of the block is written before it is read, so
+ * nothing carries over from an earlier call.  All calls on one GPU share its
+ * block: calls that overlap on one GPU (two contexts, two threads) race and
+ * must be serialised by the caller.  Kernel timing does not cover this call.
+ * Errors: as ad_score_poses; n > AD_NOALLOC_MAX_POSES -> AD_E_INVALID. */
+#define AD_NOALLOC_MAX_POSES 4096
+int ad_score_poses_noalloc(ad_ctx *ctx, const ad_batch *b, int n, const int *lig_idx, const float *genotypes,
+                           float *energy, float *grad, float *terms);
+
 /* ---- docking: Lamarckian GA + ADADELTA (Sec. 1, Sec. 1.1) ----------------
  * Per ligand, nrun independent runs.  Generation 0 evaluates pop random
  * individuals (t uniform in the grid box, uniform random orientation,

@@ -26,10 +26,11 @@ ERR_NAMES = {0: "AD_OK", -1: "AD_E_INVALID", -2: "AD_E_NOMAP", -3: "AD_E_OOM", -
              -5: "AD_E_STATE", -6: "AD_E_UNSUPPORTED", -7: "AD_E_HIP"}
 MAX_TYPES, STRIDE = 16, 40
 SHAPE_AUTO, SHAPE_WAVE64, SHAPE_WAVE128, SHAPE_PACKED = 0, 1, 2, 3
+NOALLOC_MAX_POSES = 4096   # AD_NOALLOC_MAX_POSES
 
 EXPORTS = ["ad_create", "ad_destroy", "ad_last_error", "ad_set_stream", "ad_synchronize", "ad_load_grids",
            "ad_build_grids", "ad_grid_check", "ad_ligand_check", "ad_load_ligands", "ad_load_ligands_packed", "ad_free_batch", "ad_dock_stream", "ad_batch_info",
-           "ad_score_poses", "ad_score_poses_shape", "ad_dock_batch", "ad_dock_select", "ad_local_search", "ad_local_search_shape", "ad_solis_wets", "ad_initial_population",
+           "ad_score_poses", "ad_score_poses_shape", "ad_score_poses_noalloc", "ad_dock_batch", "ad_dock_select", "ad_local_search", "ad_local_search_shape", "ad_solis_wets", "ad_initial_population",
            "ad_set_kernel_timing", "ad_get_kernel_timing", "ad_set_schedule", "ad_get_schedule",
            "ad_prescreen_n_params", "ad_prescreen_create",
            "ad_prescreen_destroy", "ad_prescreen_set_params", "ad_prescreen_get_params", "ad_prescreen_set_scale",
@@ -155,6 +156,7 @@ def lib():
     L.ad_get_kernel_timing.argtypes = [vp, C.POINTER(KernelTimes), C.c_int]
     L.ad_score_poses.argtypes = [vp, vp, C.c_int, vp, vp, vp, vp, vp, C.c_int]
     L.ad_score_poses_shape.argtypes = [vp, vp, C.c_int, vp, vp, vp, vp, vp, C.c_int, C.c_int]
+    L.ad_score_poses_noalloc.argtypes = [vp, vp, C.c_int, vp, vp, vp, vp, vp]
     L.ad_local_search_shape.argtypes = [vp, vp, C.c_int, vp, vp, vp, C.POINTER(DockParams), C.c_int, C.c_int,
                                         C.c_int]
     L.ad_dock_batch.argtypes = [vp, vp, C.POINTER(DockParams), C.c_uint64, vp, C.POINTER(DockResult), fp, fp]
@@ -435,6 +437,18 @@ class Context:
         G = np.empty((n, STRIDE), np.float32) if grad else None
         T = np.empty((n, 3), np.float32) if terms else None
         self._check(call(self.h, batch.h, n, _ptr(idx), _ptr(g), _ptr(E), _ptr(G), _ptr(T), 0))
+        return E, G, T
+
+    def ad_score_poses_noalloc(self, batch, lig_idx, genotypes, grad=False, terms=False):
+        """Host (numpy) arrays only, at most NOALLOC_MAX_POSES poses: ad_score_poses staged through
+        the library's static device block.  Returns (energy, grad, terms)."""
+        g = _np(genotypes, np.float32)
+        n = g.shape[0]
+        idx = _np(lig_idx, np.int32)
+        E = np.empty(n, np.float32)
+        G = np.empty((n, STRIDE), np.float32) if grad else None
+        T = np.empty((n, 3), np.float32) if terms else None
+        self._check(lib().ad_score_poses_noalloc(self.h, batch.h, n, _ptr(idx), _ptr(g), _ptr(E), _ptr(G), _ptr(T)))
         return E, G, T
 
     def ad_local_search(self, batch, lig_idx, genotypes, params: DockParams, iters: int, shape=None):

@@ -15,6 +15,8 @@
 
 using namespace ad;
 
+static_assert(kNoAllocPoses == AD_NOALLOC_MAX_POSES, "static staging limit matches the header");
+
 // ---------------------------------------------------------------------------
 // helpers
 // ---------------------------------------------------------------------------
@@ -169,6 +171,8 @@ extern "C" int ad_create(ad_ctx **out, int device, const ad_forcefield *ff, void
   if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return AD_E_DEVICE;
   if (device < 0 || device >= count) return AD_E_DEVICE;
   if (hipSetDevice(device) != hipSuccess) return AD_E_DEVICE;
+  // device address of ad_score_poses_noalloc's static block, once per device
+  if (noalloc_scratch_init(device) != hipSuccess) return AD_E_HIP;
   ad_ctx *c = new ad_ctx();
   c->device = device;
   c->ff = *ff;
@@ -682,6 +686,44 @@ extern "C" int ad_score_poses_shape(ad_ctx *c, const ad_batch *b, int n, const i
   if (terms) HIP_TRY(c, hipMemcpyAsync(terms, d_t, (size_t)n * 12, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->timing_collect();
+  return AD_OK;
+}
+
+extern "C" int ad_score_poses_noalloc(ad_ctx *c, const ad_batch *b, int n, const int *lig_idx,
+                                      const float *genotypes, float *energy, float *grad, float *terms) {
+  // ad_score_poses with host buffers, staged through the device's static
+  // block instead of the context's grow-only staging buffer: no device
+  // allocation, no event creation (kernel timing does not cover this call)
+  if (!c) return AD_E_INVALID;
+  int rc = check_batch(c, b);
+  if (rc) return rc;
+  if (n < 0) return c->fail(AD_E_INVALID, "n < 0");
+  if (n > kNoAllocPoses)
+    return c->fail(AD_E_INVALID, "ad_score_poses_noalloc: n = " + std::to_string(n) + " exceeds the static limit of " +
+                                     std::to_string(kNoAllocPoses) + " poses per call");
+  if (n == 0) return AD_OK;
+  if (!lig_idx || !genotypes || !energy) return c->fail(AD_E_INVALID, "null argument");
+  rc = check_shape_poses(c, b, n, lig_idx, AD_SHAPE_AUTO);
+  if (rc) return rc;
+  const int cap = shape_cap(b, AD_SHAPE_AUTO);
+  HIP_TRY(c, hipSetDevice(c->device));
+  char *blk = (char *)noalloc_scratch(c->device);
+  if (!blk) return c->fail(AD_E_STATE, "static staging block not set up on this device");
+  const EvalConst C = c->eval_const(b);
+  int *d_idx = (int *)(blk + kNoAllocIdx);
+  float *d_geo = (float *)(blk + kNoAllocGeno);
+  float *d_e = (float *)(blk + kNoAllocE);
+  float *d_g = grad ? (float *)(blk + kNoAllocG) : nullptr;
+  float *d_t = terms ? (float *)(blk + kNoAllocT) : nullptr;
+  // every staged section is written before it is read (inputs by the copies
+  // below, outputs by the kernel for every pose), so nothing needs clearing
+  HIP_TRY(c, hipMemcpyAsync(d_idx, lig_idx, (size_t)n * 4, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(d_geo, genotypes, (size_t)n * kStride * 4, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, launch_score(C, cap, n, d_idx, d_geo, d_e, d_g, d_t, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(energy, d_e, (size_t)n * 4, hipMemcpyDeviceToHost, c->stream));
+  if (grad) HIP_TRY(c, hipMemcpyAsync(grad, d_g, (size_t)n * kStride * 4, hipMemcpyDeviceToHost, c->stream));
+  if (terms) HIP_TRY(c, hipMemcpyAsync(terms, d_t, (size_t)n * 12, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
   return AD_OK;
 }
 

@@ -82,6 +82,24 @@ hipError_t launch_score(const EvalConst &C, int cap, int n, const int *lig_idx, 
 hipError_t launch_local_search(const EvalConst &C, int cap, int n, const int *lig_idx, float *geno, float *E,
                                int iters, double rho, double eps, hipStream_t s);
 hipError_t launch_build_maps(const MapBuildArgs *dev_args, size_t nn, hipStream_t s);
+
+// static staging block of ad_score_poses_noalloc (sections at fixed offsets,
+// each a multiple of 256 bytes)
+constexpr int kNoAllocPoses = 4096;
+constexpr int kNoAllocDevices = 64;
+constexpr size_t kNoAllocIdx = 0;
+constexpr size_t kNoAllocGeno = kNoAllocIdx + (size_t)kNoAllocPoses * 4;
+constexpr size_t kNoAllocE = kNoAllocGeno + (size_t)kNoAllocPoses * kStride * 4;
+constexpr size_t kNoAllocG = kNoAllocE + (size_t)kNoAllocPoses * 4;
+constexpr size_t kNoAllocT = kNoAllocG + (size_t)kNoAllocPoses * kStride * 4;
+constexpr size_t kNoAllocBytes = kNoAllocT + (size_t)kNoAllocPoses * 3 * 4;
+static_assert(kNoAllocGeno % 256 == 0 && kNoAllocE % 256 == 0 && kNoAllocG % 256 == 0 && kNoAllocT % 256 == 0 &&
+                  kNoAllocBytes % 256 == 0,
+              "noalloc sections are 256-byte aligned");
+// once per device, with that device current: takes the device address of the
+// static block (kept per device); noalloc_scratch returns it (null before)
+hipError_t noalloc_scratch_init(int device);
+void *noalloc_scratch(int device);
 hipError_t launch_relayout(const float *soa, float *out4, size_t nn, int n_maps, hipStream_t s);
 
 }  // namespace ad

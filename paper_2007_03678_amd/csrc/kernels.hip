@@ -20,6 +20,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "api_internal.h"
 
@@ -1448,6 +1449,38 @@ hipError_t launch_score(const EvalConst &C, int cap, int n, const int *lig_idx, 
     else hipLaunchKernelGGL((k_score<128, false>), grid, block, 0, s, C, n, lig_idx, geno, E, G, T);
   }
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Static staging block of ad_score_poses_noalloc: index, genotype, energy,
+// gradient and terms sections for up to kNoAllocPoses poses at fixed
+// offsets.  Each device that loads the library holds its own copy until the
+// process ends.  Host code never uses the array's name as an address: its
+// device address is taken once per device (noalloc_scratch_init, called by
+// ad_create with that device current) and every copy or kernel argument
+// uses that address.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) char scratch[kNoAllocBytes];
+
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kNoAllocDevices];
+
+hipError_t noalloc_scratch_init(int device) {
+  if (device < 0 || device >= kNoAllocDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (!ptr) return hipErrorInvalidSymbol;
+  g_scratch_ptr[device] = ptr;
+  return hipSuccess;
+}
+
+void *noalloc_scratch(int device) {
+  if (device < 0 || device >= kNoAllocDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[device];
 }
 
 hipError_t launch_local_search(const EvalConst &C, int cap, int n, const int *lig_idx, float *geno, float *E,

@@ -133,3 +133,9 @@ def test_grid_check_rejects_index_overflow(pkg):
     for bad in (synth.Grid((1, 40, 40), 0.375, (0, 0, 0), [0]), synth.Grid((40, 40, 40), 0.0, (0, 0, 0), [0]),
                 synth.Grid((40, 40, 40), 0.375, (0, 0, 0), [0, 0]), synth.Grid((40, 40, 40), 0.375, (0, 0, 0), [9])):
         assert pkg.ad_grid_check(bad, 8)[0] == pkg.AD_E_INVALID
+
+
+def test_noalloc_limit_matches_the_header(pkg):
+    txt = open(os.path.join(ROOT, "include", "addock.h")).read()
+    m = re.search(r"#define AD_NOALLOC_MAX_POSES (\d+)", txt)
+    assert m and int(m.group(1)) == pkg.NOALLOC_MAX_POSES
