@@ -278,6 +278,7 @@ def batch_leg(args, log_fn):
     kt = ctx.ad_get_kernel_timing(reset=True)
     ctx.ad_set_kernel_timing(False)
     sched = ctx.ad_get_schedule()
+    shape = ctx.ad_get_launch_shape()
     n_ls = int(np.floor(dock["ls_rate"] * dock["pop"] + 0.5))
     ls_flop = dock["nrun"] * n_ls * dock["ls_iters"] * sum(flops_per_eval(i, True) for i in infos)
     ls_ms, ls_n = kt["ls"]
@@ -293,7 +294,7 @@ def batch_leg(args, log_fn):
         "step_s": round(dt, 2),
         "generations": int(r["generations"][0]),
         "buckets": {"le64_atoms": batch.n - big, "le128_atoms": big},
-        "ls_stage_pairs": sched["stage_pairs"],
+        "ls_stage_pairs": sched["stage_pairs"], "ls_pair_unroll": shape["unroll"], "ls_wg_per_cu": shape["wg_per_cu"],
         "packed_runs": sched["packed_runs"],
         "ls_phase_avg_ms": round(ls_ms / max(ls_n, 1), 3),
         "ls_phase_tflops": round(ls_flop / (ls_ms / 1e3 / max(ls_n, 1)) / 1e12, 3) if ls_n else None,
@@ -649,6 +650,7 @@ def main():
     kt = ctx.ad_get_kernel_timing(reset=True)
     ctx.ad_set_kernel_timing(False)
     schedule = ctx.ad_get_schedule()
+    shape = ctx.ad_get_launch_shape()
     # the same step replayed as a graph (kernel timing off), for comparison
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -720,7 +722,8 @@ def main():
     }
     # score-grad evaluations per second inside the local-search kernel
     out["schedule"] = {"timed_steps": {"graph": schedule["graph"], "ls_stage_pairs": schedule["stage_pairs"],
-                                       "packed_runs": schedule["packed_runs"]},
+                                       "packed_runs": schedule["packed_runs"],
+                                       "ls_pair_unroll": shape["unroll"], "ls_wg_per_cu": shape["wg_per_cu"]},
                        "graph_replay_ms_per_step": round(graph_ms, 2), "graph": schedule_graph["graph"]}
     out["score_grad_evals_per_s"] = round(dock["nrun"] * n_lig * n_ls * dock["ls_iters"] / ls_avg_s, 1)
     if not args.no_variants:

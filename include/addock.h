@@ -371,6 +371,27 @@ int ad_set_schedule(ad_ctx *ctx, int use_graph, int autotune, int stage_pairs, i
  * packed_runs: runs whose local search was packed (any may be null). */
 int ad_get_schedule(ad_ctx *ctx, int *stage_pairs, int *graph_used, int *packed_runs);
 
+/* Launch shape of the ADADELTA local-search kernel, per bucket (the target
+ * configuration's batching: work-group shape and pair-list tiling chosen by
+ * the library's autotuner per atom-count bucket).  Two dimensions, both
+ * changing speed only (bitwise the same results):
+ *   unroll     the pair loop handles 1 or 2 of each lane's pairs per
+ *              iteration (each lane still adds its pairs in list order);
+ *   wg_per_cu  one-wavefront work-groups resident per compute unit: as many
+ *              as the kernel's LDS allows (at most 16), or fewer by padding
+ *              the dynamic LDS (fewer individuals share a CU's caches).
+ * With autotune (ad_set_schedule) each dock call's buckets time unroll
+ * {1, 2} x wg_per_cu {all, 3/4, 1/2 of what fits} on a sample of their runs
+ * (cached per batch and call shape), then the pair-staging sizes; a
+ * candidate replaces the default only if it is 3 % faster.
+ * ad_set_launch_shape forces unroll (1 or 2) and/or wg_per_cu (1..64, capped
+ * at what fits); 0 leaves a dimension to the tuner (the default).
+ * ad_get_launch_shape: unroll[2] and wg_per_cu[2] used per bucket (<= 64,
+ * <= 128 atoms) by the last dock call (-1: bucket empty, no local search, or
+ * Solis-Wets).  AD_E_INVALID for values out of range. */
+int ad_set_launch_shape(ad_ctx *ctx, int unroll, int wg_per_cu);
+int ad_get_launch_shape(ad_ctx *ctx, int *unroll, int *wg_per_cu);
+
 /* ---- diagnostics ----------------------------------------------------------
  * Kernel timing with HIP events recorded on the context's stream around
  * every launch of the docking and scoring kernels, for throughput and

@@ -31,7 +31,8 @@ NOALLOC_MAX_POSES = 4096   # AD_NOALLOC_MAX_POSES
 EXPORTS = ["ad_create", "ad_destroy", "ad_last_error", "ad_set_stream", "ad_synchronize", "ad_load_grids",
            "ad_build_grids", "ad_grid_check", "ad_ligand_check", "ad_load_ligands", "ad_load_ligands_packed", "ad_free_batch", "ad_dock_stream", "ad_batch_info",
            "ad_score_poses", "ad_score_poses_shape", "ad_score_poses_noalloc", "ad_dock_batch", "ad_dock_select", "ad_local_search", "ad_local_search_shape", "ad_solis_wets", "ad_initial_population",
-           "ad_set_kernel_timing", "ad_get_kernel_timing", "ad_set_schedule", "ad_get_schedule",
+           "ad_set_kernel_timing", "ad_get_kernel_timing", "ad_set_schedule", "ad_get_schedule", "ad_set_launch_shape",
+           "ad_get_launch_shape",
            "ad_prescreen_n_params", "ad_prescreen_create",
            "ad_prescreen_destroy", "ad_prescreen_set_params", "ad_prescreen_get_params", "ad_prescreen_set_scale",
            "ad_prescreen_get_scale", "ad_prescreen_predict", "ad_prescreen_grad", "ad_prescreen_train"]
@@ -167,6 +168,8 @@ def lib():
     L.ad_initial_population.argtypes = [vp, vp, C.c_int, C.c_uint32, C.c_int, C.c_int, C.c_uint64, fp]
     L.ad_set_schedule.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int]
     L.ad_get_schedule.argtypes = [vp, ip, ip, ip]
+    L.ad_set_launch_shape.argtypes = [vp, C.c_int, C.c_int]
+    L.ad_get_launch_shape.argtypes = [vp, ip, ip]
     L.ad_prescreen_n_params.argtypes = []
     L.ad_prescreen_create.argtypes = [vp, C.POINTER(PrescreenCfg), C.c_uint64, C.POINTER(vp)]
     L.ad_prescreen_destroy.argtypes = [vp]
@@ -361,6 +364,15 @@ class Context:
         g, pk = C.c_int(), C.c_int()
         self._check(lib().ad_get_schedule(self.h, st, C.byref(g), C.byref(pk)))
         return dict(stage_pairs=[st[0], st[1]], graph=bool(g.value), packed_runs=pk.value)
+
+    def ad_set_launch_shape(self, unroll=0, wg_per_cu=0):
+        """Force the local search's pair-loop unroll (1, 2) and/or work-groups per CU; 0: tuned."""
+        self._check(lib().ad_set_launch_shape(self.h, int(unroll), int(wg_per_cu)))
+
+    def ad_get_launch_shape(self):
+        u, w = (C.c_int * 2)(), (C.c_int * 2)()
+        self._check(lib().ad_get_launch_shape(self.h, u, w))
+        return dict(unroll=[u[0], u[1]], wg_per_cu=[w[0], w[1]])
 
     def ad_synchronize(self):
         self._check(lib().ad_synchronize(self.h))

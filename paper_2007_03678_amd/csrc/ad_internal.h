@@ -35,10 +35,11 @@ struct alignas(32) AtomGeo {
 };
 
 struct alignas(16) AtomInfo {
-  int map;      // affinity map index of the atom's type
-  float q;      // partial charge
-  int owner;    // deepest torsion whose moving set holds the atom (-1: root fragment)
-  int type;     // force-field type
+  int map;        // affinity map index of the atom's type
+  float q;        // partial charge
+  int owner;      // deepest torsion whose moving set holds the atom (-1: root fragment)
+  int16_t type;   // force-field type
+  int16_t slot;   // prefix-sum slot of the atom (-1: no torsion range ends at it), see TorRec
 };
 
 // Intramolecular pair (16 bytes): i, j (internal order) and the type-pair
@@ -56,12 +57,18 @@ struct alignas(16) PairRec {
 // unit direction u; parent torsion (-1: hangs off the root fragment);
 // moving set = internal atoms [s, e); root-side atom a and leaf-side atom b
 // (internal indices); 1/|y_b - y_a| (bond length is pose invariant).
+// The gradient needs the prefix sums over the internal order only where a
+// moving set ends (atoms e - 1 and s - 1) and at the last atom (the totals):
+// those atoms own the ligand's prefix-sum slots, slot 0 for the last atom and
+// the others in increasing atom order, at most min(2T + 1, N) of them.
+// s_slot / e_slot are the slots of atoms s - 1 (-1 when s = 0) and e - 1.
 struct alignas(16) TorRec {
   double o[3];
   double u[3];
   double inv_len;
   int parent, s, e, a, b;
   int depth;      // torsions on the path from the root, this one included
+  int s_slot, e_slot;
 };
 
 // 12-6 / 12-10 coefficients of a type pair (weights folded in).

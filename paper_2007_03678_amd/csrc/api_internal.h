@@ -47,6 +47,10 @@ struct DockArgs {
   int stage_pairs;   // local search: pair records staged in LDS per ligand (0: none)
   int n_dual;        // ADADELTA: the first n_dual runs of run_order (whole ligands of at most
                      // kDualAtoms atoms and kDualTor torsions) take the two-per-wavefront kernel
+  // launch shape of the local search (speed only, bitwise the same results):
+  // pair-loop unroll (1 or 2) and extra dynamic LDS per work-group that caps
+  // the work-groups resident per CU (0: as many as the kernel's LDS allows)
+  int ls_unroll, ls_pad;
   // Solis-Wets local search
   int ls_method;     // 0 ADADELTA, 1 Solis-Wets
   float sw_rho, sw_rho_lb, sw_sig_t, sw_sig_ang;
@@ -71,6 +75,9 @@ hipError_t launch_dock_init(const EvalConst &C, int cap, const DockArgs &D, hipS
 hipError_t launch_ga_generation(const EvalConst &C, int cap, const DockArgs &D, int gen, hipStream_t s);
 hipError_t launch_ls_generation(const EvalConst &C, int cap, const DockArgs &D, int gen, hipStream_t s);
 size_t ls_dynamic_lds(const EvalConst &C, const DockArgs &D);
+// LDS of one local-search work-group of the bucket (static + dynamic, pad
+// excluded): the tuner sizes its occupancy candidates from it
+size_t ls_workgroup_lds(const EvalConst &C, int cap, const DockArgs &D);
 hipError_t launch_dock_finalize(const DockArgs &D, int buf, float *best_E, float *best_G, hipStream_t s);
 hipError_t launch_run_status(const DockArgs &D, int gen, hipStream_t s);
 hipError_t launch_solis_wets(const EvalConst &C, int cap, const DockArgs &D, int n, const int *lig_idx, float *geno,
@@ -126,6 +133,12 @@ struct ad_batch {
   int map_of_type[AD_MAX_TYPES];   // map index of each type used by the batch at load time (-1: unused)
 };
 
+// a bucket's local-search schedule: staged pair records, pair-loop unroll,
+// work-groups resident per CU
+struct LsChoice {
+  int stage = 0, unroll = 1, wg_per_cu = 0;
+};
+
 struct ad_ctx {
   static constexpr int kScratchSlots = 4;
   // live children (batches, pre-screens): ad_destroy releases their device
@@ -173,8 +186,10 @@ struct ad_ctx {
   bool pack_small = true;   // two small ligands' individuals per wavefront in the local search
   hipStream_t aux_stream = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-  std::map<std::vector<int64_t>, int> tune_cache;
+  std::map<std::vector<int64_t>, LsChoice> tune_cache;
+  int forced_unroll = 0, forced_wgcu = 0;   // 0: tuned
   int last_stage[2] = {-1, -1};
+  int last_unroll[2] = {-1, -1}, last_wgcu[2] = {-1, -1};
   int last_graph = 0;
   int last_packed = 0;      // runs of the last dock call packed two individuals per wavefront
   uint64_t next_batch_uid = 1;

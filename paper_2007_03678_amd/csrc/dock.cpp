@@ -81,39 +81,63 @@ int ensure_aux(ad_ctx *c) {
 // LDS pair-staging candidates of the local-search kernel, within the
 // work-group's LDS budget
 std::vector<int> stage_candidates(const EvalConst &C, const DockArgs &D, int cap, int max_pairs) {
-  const size_t static_lds = cap <= 64 ? 7 * 1024 : 14 * 1024;
   std::vector<int> out = {0};
   for (int ns : {128, 256, 512, 1024, 2048}) {
     DockArgs t = D;
     t.stage_pairs = ns;
-    if (static_lds + ls_dynamic_lds(C, t) > 64 * 1024) break;
+    if (ls_workgroup_lds(C, cap, t) > 64 * 1024) break;
     out.push_back(ns);
     if (ns >= max_pairs) break;   // every pair of the bucket already staged
   }
   return out;
 }
 
-// The pair-staging size of one bucket's local-search launches: forced, from
-// the cache, or timed.  Timing runs the bucket's local search (few
-// iterations) from the evaluated initial population on a copy of the
-// population buffers, once per candidate, on a strided sample of its runs;
-// the docking state itself is not touched.  Every candidate computes the
-// same values, so the choice affects speed only.
-int choose_stage(ad_ctx *c, const ad_batch *b, const int *sel, int n_lig, const EvalConst &C, const DockArgs &Dk,
-                 int cap, int max_pairs, int *out) {
-  const std::vector<int> cand = stage_candidates(C, Dk, cap, max_pairs);
-  if (c->forced_stage >= 0) {
-    int pick = 0;
-    for (int ns : cand)
-      if (ns <= c->forced_stage) pick = ns;
-    *out = pick;
+// Launch schedule of one bucket's local search, chosen by timing: the shape
+// (pair-loop unroll 1 or 2; work-groups resident per CU: as many as the LDS
+// allows, three quarters or half of that, set by padding the dynamic LDS)
+// and the number of pair records staged in LDS.  Timing runs the bucket's
+// local search (few iterations) from the evaluated initial population on a
+// copy of the population buffers, once per candidate (best of three), on a
+// strided sample of its runs; the docking state itself is not touched.
+// Every candidate computes bitwise the same values, so the choice affects
+// speed only.  A candidate replaces the default (unroll 1, full occupancy,
+// no staging) only if it is 3 % faster.  Forced values (ad_set_schedule,
+// ad_set_launch_shape) are taken as given.
+constexpr int kLdsPerCU = 160 * 1024;
+constexpr int kMaxWgPerCU = 16;   // 4 one-wavefront work-groups per SIMD (the kernel's VGPR budget)
+
+int natural_wg_per_cu(size_t lds) { return std::max(1, std::min(kMaxWgPerCU, (int)(kLdsPerCU / std::max<size_t>(lds, 1)))); }
+
+// dynamic-LDS pad that leaves `target` work-groups per CU (0: none needed)
+int pad_for(size_t lds, int target) {
+  if (target <= 0 || target >= natural_wg_per_cu(lds)) return 0;
+  const size_t want = ((size_t)(kLdsPerCU / target) / 512) * 512;   // an LDS granule below 1/target of the CU
+  return want > lds ? (int)(want - lds) : 0;
+}
+
+int choose_schedule(ad_ctx *c, const ad_batch *b, const int *sel, int n_lig, const EvalConst &C, const DockArgs &Dk,
+                    int cap, int max_pairs, bool stage_ok, LsChoice *out) {
+  const int bk = cap > 64 ? 1 : 0;
+  LsChoice best;
+  best.stage = 0;
+  best.unroll = c->forced_unroll > 0 ? c->forced_unroll : 1;
+  best.wg_per_cu = 0;
+  const size_t lds0 = ls_workgroup_lds(C, cap, Dk);
+  const int natural = natural_wg_per_cu(lds0);
+  const std::vector<int> stage_cand = stage_ok ? stage_candidates(C, Dk, cap, max_pairs) : std::vector<int>{0};
+  if (c->forced_wgcu > 0) best.wg_per_cu = std::min(c->forced_wgcu, natural);
+  if (c->forced_stage >= 0)
+    for (int ns : stage_cand)
+      if (ns <= c->forced_stage) best.stage = ns;
+  const bool tune_shape = c->autotune && (c->forced_unroll <= 0 || c->forced_wgcu <= 0);
+  const bool tune_stage = c->autotune && c->forced_stage < 0 && stage_cand.size() > 1;
+  if (!tune_shape && !tune_stage) {
+    if (best.wg_per_cu <= 0) best.wg_per_cu = natural;
+    *out = best;
     return AD_OK;
   }
-  if (!c->autotune || cand.size() < 2) {
-    *out = 0;
-    return AD_OK;
-  }
-  std::vector<int64_t> key = {(int64_t)b->uid, cap, Dk.pop, Dk.n_ls, Dk.n_launch, n_lig};
+  std::vector<int64_t> key = {(int64_t)b->uid, cap, Dk.pop, Dk.n_ls, Dk.n_launch, n_lig, Dk.n_dual,
+                              c->forced_unroll, c->forced_wgcu, c->forced_stage};
   if (sel) {
     uint64_t h = 1469598103934665603ull;
     for (int l = 0; l < n_lig; ++l) h = (h ^ (uint64_t)sel[l]) * 1099511628211ull;
@@ -124,36 +148,46 @@ int choose_stage(ad_ctx *c, const ad_batch *b, const int *sel, int n_lig, const 
     *out = it->second;
     return AD_OK;
   }
-  const int K = std::min(Dk.n_launch, std::max(1, 3072 / std::max(1, Dk.n_ls)) * 2);
+  // timing sample: single-wavefront runs when the bucket has any (packed
+  // runs take the same shape), else its first whole packed ligands
+  const int n_single = Dk.n_launch - Dk.n_dual;
   const size_t pop_floats = (size_t)Dk.n_runs * Dk.pop;
   const size_t sz_g = align256(pop_floats * kStride * sizeof(float));
   const size_t sz_e = align256(pop_floats * sizeof(float));
   const size_t sz_v = align256((size_t)Dk.n_runs * sizeof(unsigned long long));
-  const size_t sz_o = align256((size_t)K * sizeof(int));
+  const size_t sz_o = align256((size_t)Dk.n_launch * sizeof(int));
   char *blk = (char *)c->scratch_alloc(sz_g + sz_e + sz_v + sz_o, 3);
   if (!blk) return c->fail(AD_E_OOM, "cannot allocate autotuning buffers");
-  std::vector<int> host_order(Dk.n_launch), sample(K);
+  std::vector<int> host_order(Dk.n_launch), sample;
   HIP_TRY(c, hipMemcpyAsync(host_order.data(), Dk.run_order, Dk.n_launch * sizeof(int), hipMemcpyDeviceToHost,
                             c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  for (int k = 0; k < K; ++k) sample[k] = host_order[(size_t)k * Dk.n_launch / K];
   DockArgs T = Dk;
+  if (n_single > 0) {
+    const int K = std::min(n_single, std::max(1, 3072 / std::max(1, Dk.n_ls)) * 2);
+    for (int k = 0; k < K; ++k) sample.push_back(host_order[Dk.n_dual + (size_t)k * n_single / K]);
+    T.n_dual = 0;
+  } else {
+    const int lig_runs = std::max(1, std::min(Dk.n_dual / Dk.nrun, std::max(1, 6144 / std::max(1, Dk.nrun * Dk.n_ls))));
+    sample.assign(host_order.begin(), host_order.begin() + (size_t)lig_runs * Dk.nrun);
+    T.n_dual = (int)sample.size();
+  }
   T.geno = (float *)blk;
   T.energy = (float *)(blk + sz_g);
   T.evals = (unsigned long long *)(blk + sz_g + sz_e);
   int *d_sample = (int *)(blk + sz_g + sz_e + sz_v);
   T.run_order = d_sample;
-  T.n_launch = K;
+  T.n_launch = (int)sample.size();
   T.ls_iters = std::min(Dk.ls_iters, 24);
-  HIP_TRY(c, hipMemcpyAsync(d_sample, sample.data(), K * sizeof(int), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(d_sample, sample.data(), sample.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
   hipEvent_t e0, e1;
   HIP_TRY(c, hipEventCreate(&e0));
   HIP_TRY(c, hipEventCreate(&e1));
-  int best = 0;
-  float best_ms = INFINITY;
   int rc = AD_OK;
-  for (int ns : cand) {
-    T.stage_pairs = ns;
+  auto time_ms = [&](const LsChoice &ch, float *ms_out) {
+    T.stage_pairs = ch.stage;
+    T.ls_unroll = ch.unroll;
+    T.ls_pad = pad_for(ls_workgroup_lds(C, cap, T), ch.wg_per_cu);
     float ms_min = INFINITY;
     for (int rep = 0; rep < 3 && rc == AD_OK; ++rep) {
       hipError_t e = hipMemcpyAsync(T.geno, Dk.geno, pop_floats * kStride * sizeof(float), hipMemcpyDeviceToDevice,
@@ -169,17 +203,53 @@ int choose_stage(ad_ctx *c, const ad_batch *b, const int *sel, int n_lig, const 
       if (e != hipSuccess) rc = c->hip_fail(e, "autotuning launch");
       ms_min = std::min(ms_min, ms);
     }
-    if (rc) break;
-    // a larger staging size must win by 3 % (timing noise and the LDS it
-    // takes from co-resident work-groups of other launches)
-    if (ms_min < 0.97f * best_ms) {
-      best_ms = ms_min;
-      best = ns;
+    *ms_out = ms_min;
+  };
+  if (best.wg_per_cu <= 0) best.wg_per_cu = natural;
+  float best_ms = INFINITY;
+  time_ms(best, &best_ms);
+  if (tune_shape) {
+    std::vector<int> unrolls = c->forced_unroll > 0 ? std::vector<int>{c->forced_unroll} : std::vector<int>{1, 2};
+    std::vector<int> occ = c->forced_wgcu > 0 ? std::vector<int>{best.wg_per_cu}
+                                              : std::vector<int>{natural, (3 * natural + 2) / 4, (natural + 1) / 2};
+    const LsChoice base = best;
+    for (int u : unrolls)
+      for (int w : occ) {
+        LsChoice ch = base;
+        ch.unroll = u;
+        ch.wg_per_cu = std::max(1, w);
+        if (ch.unroll == base.unroll && ch.wg_per_cu == base.wg_per_cu) continue;
+        float ms;
+        time_ms(ch, &ms);
+        if (rc) break;
+        if (ms < 0.97f * best_ms) {
+          best_ms = ms;
+          best = ch;
+        }
+      }
+  }
+  if (tune_stage && rc == AD_OK) {
+    // staged records run the plain (unroll 1) loop; a larger staging size
+    // must win by 3 % (timing noise and the LDS it takes from co-resident
+    // work-groups of other launches)
+    for (int ns : stage_cand) {
+      if (ns == 0) continue;
+      LsChoice ch = best;
+      ch.stage = ns;
+      ch.unroll = 1;
+      float ms;
+      time_ms(ch, &ms);
+      if (rc) break;
+      if (ms < 0.97f * best_ms) {
+        best_ms = ms;
+        best = ch;
+      }
     }
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   if (rc) return rc;
+  (void)bk;
   c->tune_cache[key] = best;
   *out = best;
   return AD_OK;
@@ -261,6 +331,8 @@ int dock_impl(ad_ctx *c, const ad_batch *b, int n_lig, const int *sel, const ad_
     return ptr;
   };
   DockArgs D;
+  memset(&D, 0, sizeof(D));
+  D.ls_unroll = 1;
   D.geno = (float *)carve(sz_geno);
   D.energy = (float *)carve(sz_E);
   D.evals = (unsigned long long *)carve(sz_ev);
@@ -375,16 +447,23 @@ int dock_impl(ad_ctx *c, const ad_batch *b, int n_lig, const int *sel, const ad_
   const bool do_ls = n_ls > 0 && p->ls_iters > 0;
   for (int bk = 0; bk < 2; ++bk) {
     c->last_stage[bk] = -1;
+    c->last_unroll[bk] = -1;
+    c->last_wgcu[bk] = -1;
     if (!Db[bk].n_launch || !do_ls) continue;
-    int st = 0;
-    if (p->ls_method == 1 || Db[bk].n_dual > 0) {   // no pair staging: Solis-Wets, or packed runs
+    if (p->ls_method == 1) {   // Solis-Wets: its own kernel, one fixed shape
       c->last_stage[bk] = 0;
       continue;
     }
-    rc = choose_stage(c, b, sel, n_lig, C, Db[bk], bk ? 128 : 64, max_pairs[bk], &st);
+    // packed runs stage no pairs; their launch still takes the tuned shape
+    LsChoice ch;
+    rc = choose_schedule(c, b, sel, n_lig, C, Db[bk], bk ? 128 : 64, max_pairs[bk], Db[bk].n_dual == 0, &ch);
     if (rc) return rc;
-    Db[bk].stage_pairs = st;
-    c->last_stage[bk] = st;
+    Db[bk].stage_pairs = ch.stage;
+    Db[bk].ls_unroll = ch.unroll;
+    Db[bk].ls_pad = pad_for(ls_workgroup_lds(C, bk ? 128 : 64, Db[bk]), ch.wg_per_cu);
+    c->last_stage[bk] = ch.stage;
+    c->last_unroll[bk] = ch.unroll;
+    c->last_wgcu[bk] = ch.wg_per_cu;
   }
 
   // the generation loop: bucket 0 on the context's stream, bucket 1 on the
@@ -619,6 +698,24 @@ extern "C" int ad_set_schedule(ad_ctx *c, int use_graph, int autotune, int stage
   c->pack_small = pack_small != 0;
   c->autotune = autotune != 0;
   c->forced_stage = stage_pairs < 0 ? -1 : stage_pairs;
+  return AD_OK;
+}
+
+extern "C" int ad_set_launch_shape(ad_ctx *c, int unroll, int wg_per_cu) {
+  if (!c) return AD_E_INVALID;
+  if (unroll < 0 || unroll > 2 || wg_per_cu < 0 || wg_per_cu > 64)
+    return c->fail(AD_E_INVALID, "launch shape: unroll 0 (tune), 1 or 2; wg_per_cu 0 (tune) or 1..64");
+  c->forced_unroll = unroll;
+  c->forced_wgcu = wg_per_cu;
+  return AD_OK;
+}
+
+extern "C" int ad_get_launch_shape(ad_ctx *c, int *unroll, int *wg_per_cu) {
+  if (!c) return AD_E_INVALID;
+  for (int bk = 0; bk < 2; ++bk) {
+    if (unroll) unroll[bk] = c->last_unroll[bk];
+    if (wg_per_cu) wg_per_cu[bk] = c->last_wgcu[bk];
+  }
   return AD_OK;
 }
 

@@ -237,11 +237,14 @@ __device__ __forceinline__ double wrap_angle(double th) {
 // ---------------------------------------------------------------------------
 template <int CAP, int NT = kMaxTor>
 struct EvalLds {
+  // prefix-sum slots: at most one per torsion range end and start, plus the
+  // totals, and never more than the atoms
+  static constexpr int kSlots = 2 * NT + 1 < CAP ? 2 * NT + 1 : CAP;
   double x[3][CAP];   // posed coordinates (component-major)
   double g[CAP][3];   // dE/dx accumulators
   union {
     double tm[NT][12];        // torsion rigid transforms T_k = (R_k | w_k) (pose phase)
-    double pre[CAP][6];       // inclusive prefix sums of (g, (x-t) x g) (gradient phase)
+    double pre[kSlots][6];    // inclusive prefix sums of (g, (x-t) x g) at the slot atoms (gradient phase)
   };
   int tpar[NT];               // parent torsion of each torsion (-1: root fragment)
   double geno[kStride];        // genotype being evaluated
@@ -278,9 +281,9 @@ struct LaneLig {
   static constexpr int kAPL = CAP >= 64 ? CAP / 64 : 1;
   LigDesc L;
   double y[kAPL][3];
-  int map[kAPL], owner[kAPL];
+  int map[kAPL], owner[kAPL], slot[kAPL];
   float q[kAPL];
-  int ts, te, ta, tb;
+  int ts, te, ta, tb;   // ts, te: prefix-sum slots of the torsion's range (TorRec s_slot, e_slot)
   double tinv;
   __device__ void load(const EvalConst &C, int li, int lane) {
     L = C.batch.lig[li];
@@ -292,15 +295,15 @@ struct LaneLig {
         const AtomGeo &ag = C.batch.geo[L.atom_off + i];
         const AtomInfo &ai = C.batch.info[L.atom_off + i];
         y[c][0] = ag.y[0]; y[c][1] = ag.y[1]; y[c][2] = ag.y[2];
-        map[c] = ai.map; q[c] = ai.q; owner[c] = ai.owner;
+        map[c] = ai.map; q[c] = ai.q; owner[c] = ai.owner; slot[c] = ai.slot;
       } else {
         y[c][0] = y[c][1] = y[c][2] = 0.0;
-        map[c] = 0; q[c] = 0.0f; owner[c] = -1;
+        map[c] = 0; q[c] = 0.0f; owner[c] = -1; slot[c] = -1;
       }
     }
     if (lane < L.n_tor) {
       const TorRec &tr = C.batch.tors[L.tor_off + lane];
-      ts = tr.s; te = tr.e; ta = tr.a; tb = tr.b; tinv = tr.inv_len;
+      ts = tr.s_slot; te = tr.e_slot; ta = tr.a; tb = tr.b; tinv = tr.inv_len;
     } else {
       ts = te = ta = tb = 0; tinv = 0.0;
     }
@@ -425,7 +428,7 @@ struct PairStage {
   int off, n;
 };
 
-template <int CAP, bool GRAD, bool STAGE = false, int W = 64, int NT = kMaxTor>
+template <int CAP, bool GRAD, bool STAGE = false, int W = 64, int NT = kMaxTor, int UNROLL = 1>
 __device__ double evaluate(const EvalConst &C, const LaneLig<CAP> &LL, EvalLds<CAP, NT> &S, int lane, double *inter_out,
                            double *intra_out, PairStage st = PairStage{0, 0}, int half = 0) {
   constexpr int APL = CAP / W;
@@ -517,6 +520,9 @@ __device__ double evaluate(const EvalConst &C, const LaneLig<CAP> &LL, EvalLds<C
     rec_b = (STAGE && lane + W < st.n) ? s_pr[lane + W] : pr[lane + W];
     lj_a = STAGE ? s_lj[rec_a.ijt >> 16] : ljt[rec_a.ijt >> 16];
   }
+  // UNROLL (a launch-shape option of the local search) only unrolls the
+  // loop: every lane adds its pairs' energies and forces in the same order
+#pragma unroll UNROLL
   for (int p = lane; p < L.n_pairs; p += W) {
     const PairRec rec = rec_a;
     const LJRec lj = lj_a;
@@ -577,15 +583,14 @@ __device__ double evaluate(const EvalConst &C, const LaneLig<CAP> &LL, EvalLds<C
 #pragma unroll
     for (int e = 0; e < 6; ++e) {
       double s = grp_incl_scan<W>(vv[c][e]) + carry[e];
-      if (i < L.n_atoms) S.pre[i][e] = s;
+      if (i < L.n_atoms && LL.slot[c] >= 0) S.pre[LL.slot[c]][e] = s;
       carry[e] = grp_last<W>(s, half);
     }
   }
   __syncthreads();
-  const int nl = L.n_atoms - 1;
   if (lane < kStride && lane < W) {
     double gv = 0.0;
-    if (lane < 6) gv = S.pre[nl][lane];   // dE/dt and dE/domega: totals
+    if (lane < 6) gv = S.pre[0][lane];   // dE/dt and dE/domega: totals (the last atom's slot)
     S.grad[lane] = gv;
   }
   if (lane < L.n_tor) {
@@ -593,7 +598,7 @@ __device__ double evaluate(const EvalConst &C, const LaneLig<CAP> &LL, EvalLds<C
     const double tinv_len = LL.tinv;
     double F[6];
 #pragma unroll
-    for (int e = 0; e < 6; ++e) F[e] = S.pre[te - 1][e] - (ts > 0 ? S.pre[ts - 1][e] : 0.0);
+    for (int e = 0; e < 6; ++e) F[e] = S.pre[te][e] - (ts >= 0 ? S.pre[ts][e] : 0.0);
     const double ax = S.x[0][ta] - t0, ay = S.x[1][ta] - t1, az = S.x[2][ta] - t2;
     // torque about the axis point a: sum (x_i - t) x g_i - (x_a - t) x sum g_i
     const double tx = F[3] - (ay * F[2] - az * F[1]);
@@ -657,7 +662,7 @@ __global__ __launch_bounds__(64) void k_score(EvalConst C, int n, const int *__r
 // Degrees of freedom on lanes: 0-2 translation, 3-5 rotation vector,
 // 7..7+T-1 torsions (lane 6 is the fourth quaternion slot).
 // ---------------------------------------------------------------------------
-template <int CAP, bool STAGE = false, int W = 64, int NT = kMaxTor>
+template <int CAP, bool STAGE = false, int W = 64, int NT = kMaxTor, int UNROLL = 1>
 __device__ void adadelta_wave(const EvalConst &C, const LaneLig<CAP> &LL, EvalLds<CAP, NT> &S, int lane,
                               float *geno_io, float *E_io, int iters, double rho_d, double eps_d,
                               PairStage st = PairStage{0, 0}, int half = 0, bool write = true) {
@@ -678,7 +683,7 @@ __device__ void adadelta_wave(const EvalConst &C, const LaneLig<CAP> &LL, EvalLd
     const float rho = (float)(rho_d + zd), eps = (float)(eps_d + zd);
     if (gl) S.geno[lane] = (double)gene;
     __syncthreads();
-    const double E = evaluate<CAP, true, STAGE, W, NT>(C, LL, S, lane, nullptr, nullptr, st, half);
+    const double E = evaluate<CAP, true, STAGE, W, NT, UNROLL>(C, LL, S, lane, nullptr, nullptr, st, half);
     const double gd = dof ? S.grad[lane] : 0.0;
     if (E < best_E) {
       best_E = E;
@@ -1009,6 +1014,7 @@ __global__ __launch_bounds__(64) void k_ga_generation(EvalConst C, DockArgs D, i
 // writes nothing, so both halves pass the same barriers.  `wg` numbers the
 // packed work-groups; dynamic LDS: 2 * pop ints (each half's pick
 // permutation).
+template <int UNROLL>
 __device__ void ls_dual(const EvalConst &C, const DockArgs &D, int gen, int wg, EvalLds<kDualAtoms, kDualTor> *S2) {
   extern __shared__ __attribute__((aligned(16))) char dyn_lds[];
   const int half = threadIdx.x >> 5, lane = threadIdx.x & 31;
@@ -1043,7 +1049,8 @@ __device__ void ls_dual(const EvalConst &C, const DockArgs &D, int gen, int wg, 
   LaneLig<kDualAtoms> LL;
   LL.load(C, D.lig_map ? D.lig_map[li] : li, lane);
   const size_t off = pop_off(D, gen & 1, R) + indiv;
-  adadelta_wave<kDualAtoms, false, 32, kDualTor>(C, LL, S, lane, D.geno + off * kStride, D.energy + off, D.ls_iters,
+  adadelta_wave<kDualAtoms, false, 32, kDualTor, UNROLL>(C, LL, S, lane, D.geno + off * kStride, D.energy + off,
+                                                         D.ls_iters,
                                                  D.rho, D.eps, PairStage{0, 0}, half, live);
   if (lane == 0 && live) atomicAdd(&D.evals[R], (unsigned long long)D.ls_iters);
 }
@@ -1055,7 +1062,7 @@ __device__ void ls_dual(const EvalConst &C, const DockArgs &D, int gen, int wg, 
 // type-pair table are copied to LDS once and read from there by all
 // ls_iters evaluations (the results are bitwise the same either way).
 // Dynamic LDS: pop ints (the pick permutation), then the staged records.
-template <int CAP, bool STAGE>
+template <int CAP, bool STAGE, int UNROLL = 1>
 __global__ __launch_bounds__(64) void k_ls_generation(EvalConst C, DockArgs D, int gen) {
   // the 64-atom variant without staging also runs the packed work-groups
   // (ls_dual), after the others; both share one static LDS block
@@ -1064,7 +1071,7 @@ __global__ __launch_bounds__(64) void k_ls_generation(EvalConst C, DockArgs D, i
   __shared__ __attribute__((aligned(16))) char lds[kPack && kTwo > kOne ? kTwo : kOne];
   const int n_single = (D.n_launch - D.n_dual) * D.n_ls;
   if (kPack && (int)blockIdx.x >= n_single) {
-    ls_dual(C, D, gen, (int)blockIdx.x - n_single, reinterpret_cast<EvalLds<kDualAtoms, kDualTor> *>(lds));
+    ls_dual<UNROLL>(C, D, gen, (int)blockIdx.x - n_single, reinterpret_cast<EvalLds<kDualAtoms, kDualTor> *>(lds));
     return;
   }
   EvalLds<CAP> &S = *reinterpret_cast<EvalLds<CAP> *>(lds);
@@ -1105,7 +1112,8 @@ __global__ __launch_bounds__(64) void k_ls_generation(EvalConst C, DockArgs D, i
     __syncthreads();
   }
   const size_t off = pop_off(D, gen & 1, R) + indiv;
-  adadelta_wave<CAP, STAGE>(C, LL, S, lane, D.geno + off * kStride, D.energy + off, D.ls_iters, D.rho, D.eps, st);
+  adadelta_wave<CAP, STAGE, 64, kMaxTor, UNROLL>(C, LL, S, lane, D.geno + off * kStride, D.energy + off, D.ls_iters,
+                                                 D.rho, D.eps, st);
   if (lane == 0) atomicAdd(&D.evals[R], (unsigned long long)D.ls_iters);
 }
 
@@ -1549,10 +1557,35 @@ size_t ls_dynamic_lds(const EvalConst &C, const DockArgs &D) {
   return (size_t)stage_offset(D.pop) + (size_t)C.ff.n_types * C.ff.n_types * 16 + (size_t)D.stage_pairs * 16;
 }
 
+size_t ls_workgroup_lds(const EvalConst &C, int cap, const DockArgs &D) {
+  if (cap <= 64) {
+    const size_t one = sizeof(EvalLds<64>), two = 2 * sizeof(EvalLds<kDualAtoms, kDualTor>);
+    const bool packed = D.ls_method == 0 && D.n_dual > 0 && D.stage_pairs <= 0;
+    return (D.stage_pairs > 0 ? one : std::max(one, two)) +
+           (packed ? 2 * (size_t)D.pop * sizeof(int) : ls_dynamic_lds(C, D));
+  }
+  return sizeof(EvalLds<128>) + ls_dynamic_lds(C, D);
+}
+
+// the local-search kernel of a bucket with the launch shape's pair-loop unroll
+template <int CAP, bool STAGE>
+void launch_ls_kernel(int unroll, dim3 grid, size_t dyn, hipStream_t s, const EvalConst &C, const DockArgs &D,
+                      int gen) {
+  if constexpr (!STAGE) {   // staged pair records keep the plain loop
+    if (unroll == 2) {
+      hipLaunchKernelGGL((k_ls_generation<CAP, false, 2>), grid, dim3(64), dyn, s, C, D, gen);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((k_ls_generation<CAP, STAGE, 1>), grid, dim3(64), dyn, s, C, D, gen);
+}
+
 hipError_t launch_ls_generation(const EvalConst &C, int cap, const DockArgs &D0, int gen, hipStream_t s) {
   if (D0.n_launch <= 0 || D0.n_ls <= 0) return hipSuccess;
   const dim3 block(64);
   DockArgs D = D0;
+  const size_t pad = D0.ls_method == 0 ? (size_t)std::max(0, D0.ls_pad) : 0;
+  const int ur = D0.ls_unroll;
   if (cap <= 64 && D0.ls_method == 0 && D0.n_dual > 0 && D0.stage_pairs <= 0) {
     // packed ligands: ceil(nrun * n_ls / 2) work-groups per ligand, after the
     // single-individual ones in the same launch when the grid allows
@@ -1560,10 +1593,9 @@ hipError_t launch_ls_generation(const EvalConst &C, int cap, const DockArgs &D0,
     const long long wpl = (D0.nrun * D0.n_ls + 1) / 2;
     const long long n_chunks = D0.n_dual / D0.nrun;
     const long long n_single = (long long)(D0.n_launch - D0.n_dual) * D0.n_ls;
-    const size_t dyn = 2 * (size_t)D0.pop * sizeof(int);
+    const size_t dyn = 2 * (size_t)D0.pop * sizeof(int) + pad;
     if (n_single + n_chunks * wpl <= max_blocks) {
-      hipLaunchKernelGGL((k_ls_generation<64, false>), dim3((unsigned)(n_single + n_chunks * wpl)), block, dyn, s, C,
-                         D0, gen);
+      launch_ls_kernel<64, false>(ur, dim3((unsigned)(n_single + n_chunks * wpl)), dyn, s, C, D0, gen);
       return hipGetLastError();
     }
     DockArgs Ds = D0;
@@ -1571,32 +1603,31 @@ hipError_t launch_ls_generation(const EvalConst &C, int cap, const DockArgs &D0,
     Ds.n_launch = D0.n_launch - D0.n_dual;
     Ds.n_dual = 0;
     hipError_t e = Ds.n_launch > 0 ? for_run_chunks(Ds, D0.n_ls, [&](const DockArgs &Dc, dim3 g) {
-      hipLaunchKernelGGL((k_ls_generation<64, false>), g, block, dyn, s, C, Dc, gen);
+      launch_ls_kernel<64, false>(ur, g, dyn, s, C, Dc, gen);
     }) : hipSuccess;
     const long long step = std::max(1LL, max_blocks / wpl);
     for (long long c0 = 0; c0 < n_chunks && e == hipSuccess; c0 += step) {
       DockArgs Dc = D0;   // packed work-groups only: n_launch == n_dual
       Dc.run_order = D0.run_order + c0 * D0.nrun;
       Dc.n_dual = Dc.n_launch = (int)(std::min(step, n_chunks - c0) * D0.nrun);
-      hipLaunchKernelGGL((k_ls_generation<64, false>), dim3((unsigned)(Dc.n_dual / D0.nrun * wpl)), block, dyn, s, C,
-                         Dc, gen);
+      launch_ls_kernel<64, false>(ur, dim3((unsigned)(Dc.n_dual / D0.nrun * wpl)), dyn, s, C, Dc, gen);
       e = hipGetLastError();
     }
     return e;
   }
   D.n_dual = 0;   // every run takes one wavefront per individual
-  const size_t dyn = ls_dynamic_lds(C, D);
+  const size_t dyn = ls_dynamic_lds(C, D) + pad;
   const bool st = D.stage_pairs > 0;
   return for_run_chunks(D, D.n_ls, [&](const DockArgs &Dc, dim3 lgrid) {
     if (D.ls_method == 1) {
       if (cap <= 64) hipLaunchKernelGGL((k_sw_generation<64>), lgrid, block, (size_t)D.pop * sizeof(int), s, C, Dc, gen);
       else hipLaunchKernelGGL((k_sw_generation<128>), lgrid, block, (size_t)D.pop * sizeof(int), s, C, Dc, gen);
     } else if (cap <= 64) {
-      if (st) hipLaunchKernelGGL((k_ls_generation<64, true>), lgrid, block, dyn, s, C, Dc, gen);
-      else hipLaunchKernelGGL((k_ls_generation<64, false>), lgrid, block, dyn, s, C, Dc, gen);
+      if (st) launch_ls_kernel<64, true>(ur, lgrid, dyn, s, C, Dc, gen);
+      else launch_ls_kernel<64, false>(ur, lgrid, dyn, s, C, Dc, gen);
     } else {
-      if (st) hipLaunchKernelGGL((k_ls_generation<128, true>), lgrid, block, dyn, s, C, Dc, gen);
-      else hipLaunchKernelGGL((k_ls_generation<128, false>), lgrid, block, dyn, s, C, Dc, gen);
+      if (st) launch_ls_kernel<128, true>(ur, lgrid, dyn, s, C, Dc, gen);
+      else launch_ls_kernel<128, false>(ur, lgrid, dyn, s, C, Dc, gen);
     }
   });
 }

@@ -162,7 +162,8 @@ int prepare_ligand(const ad_ligand &L, const ad_forcefield &ff, const int *type_
     P.info[s].map = type_to_map ? type_to_map[L.type_id[i]] : 0;
     P.info[s].q = L.charge[i];
     P.info[s].owner = owner[i];
-    P.info[s].type = L.type_id[i];
+    P.info[s].type = (int16_t)L.type_id[i];
+    P.info[s].slot = -1;
   }
   // torsions in input order
   P.tors.resize(n_tor);
@@ -189,6 +190,23 @@ int prepare_ligand(const ad_ligand &L, const ad_forcefield &ff, const int *type_
     t.a = pos[aa];
     t.b = pos[bb];
     t.depth = 0;
+  }
+  // prefix-sum slots: the last atom takes slot 0, every other atom where a
+  // moving set ends (e - 1) or starts after (s - 1) one slot in atom order
+  {
+    std::vector<int> need;
+    for (int k = 0; k < n_tor; ++k) {
+      if (P.tors[k].e - 1 != n - 1) need.push_back(P.tors[k].e - 1);
+      if (P.tors[k].s > 0) need.push_back(P.tors[k].s - 1);
+    }
+    std::sort(need.begin(), need.end());
+    need.erase(std::unique(need.begin(), need.end()), need.end());
+    P.info[n - 1].slot = 0;
+    for (size_t q = 0; q < need.size(); ++q) P.info[need[q]].slot = (int16_t)(q + 1);
+    for (int k = 0; k < n_tor; ++k) {
+      P.tors[k].e_slot = P.info[P.tors[k].e - 1].slot;
+      P.tors[k].s_slot = P.tors[k].s > 0 ? P.info[P.tors[k].s - 1].slot : -1;
+    }
   }
   // nesting depth: torsions on the path root -> b, this one included
   for (int k = 0; k < n_tor; ++k) {

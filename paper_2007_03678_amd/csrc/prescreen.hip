@@ -50,7 +50,14 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 // A modes: 0 row-major A1[m*lda1 + k] (rows optionally through a_rows),
 //          1 two row-major sources side by side (k < split from A1),
 //          2 column access A1[k*lda1 + m] (a transposed operand),
-//          3 column access of two sources (m < split from A1).
+//          3 column access of two sources (m < split from A1),
+//          4 a message-passing layer's [H | r(A H)]: columns k < split are
+//            H = A1 (row-major, lda1), columns k >= split the BF16 rounding
+//            of the sum of H over the row's bond neighbours, gathered in
+//            the tile loader in neighbour order (the same FP32 sum, hence
+//            the same rounding, as a separate gather pass); the work-groups
+//            of the first N tile also store that half to Mout when given
+//            (the backward pass reads it).
 // B modes: 0 B[k*ldb + n], 1 B[n*ldb + k] (a transposed operand).
 // ---------------------------------------------------------------------------
 struct GemmArgs {
@@ -73,6 +80,10 @@ struct GemmArgs {
   int ldc16;
   float *part;            // split-K partials [gridDim.z][M][N]
   int k_chunk;
+  // a_mode 4: graph layout of the rows and where the gathered half goes
+  const int *node_atom, *node_g0;
+  const uint8_t *nbr;
+  uint16_t *Mout;
 };
 
 constexpr int BM = 64, BN = 64, BK = 32, BKP = BK + 8;
@@ -88,6 +99,14 @@ __device__ __forceinline__ uint16_t gemm_a(const GemmArgs &g, int m, int k) {
       return k < g.split ? g.A1[(size_t)m * g.lda1 + k] : g.A2[(size_t)m * g.lda2 + (k - g.split)];
     case 2:
       return g.A1[(size_t)k * g.lda1 + m];
+    case 4: {
+      if (k < g.split) return g.A1[(size_t)m * g.lda1 + k];
+      const uint8_t *nb = g.nbr + (size_t)g.node_atom[m] * kMaxDeg;
+      float acc = 0.0f;
+      for (int d = 0; d < kMaxDeg && nb[d] != 0xff; ++d)
+        acc += bf2f(g.A1[(size_t)(g.node_g0[m] + nb[d]) * g.lda1 + (k - g.split)]);
+      return f2bf(acc);
+    }
     default:
       return m < g.split ? g.A1[(size_t)k * g.lda1 + m] : g.A2[(size_t)k * g.lda2 + (m - g.split)];
   }
@@ -102,8 +121,8 @@ __device__ __forceinline__ const uint16_t *aligned8(const uint16_t *p) {
 // row-wise modes: A(m, k..k+7)
 __device__ __forceinline__ const uint16_t *a_row8(const GemmArgs &g, int m, int k, int kz1) {
   if (m >= g.M || m == g.m_ones || k + 8 > kz1) return nullptr;
-  if (g.a_mode == 0) {
-    if (g.a_rows || (g.lda1 & 7)) return nullptr;
+  if (g.a_mode == 0 || g.a_mode == 4) {
+    if (g.a_rows || (g.lda1 & 7) || (g.a_mode == 4 && k + 8 > g.split)) return nullptr;
     return aligned8(g.A1 + (size_t)m * g.lda1 + k);
   }
   if (k + 8 <= g.split) return (g.lda1 & 7) ? nullptr : aligned8(g.A1 + (size_t)m * g.lda1 + k);
@@ -135,13 +154,44 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   const int wm = wave >> 1, wn = wave & 1;
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
   const int kz0 = blockIdx.z * g.k_chunk, kz1 = min(g.K, kz0 + g.k_chunk);
-  const bool a_rowwise = g.a_mode <= 1;
+  const bool a_rowwise = g.a_mode <= 1 || g.a_mode == 4;
   f32x16 acc;
 #pragma unroll
   for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
   for (int k0 = kz0; k0 < kz1; k0 += BK) {
     // A tile (64 x 32): each thread moves 8 elements along the contiguous axis
-    if (a_rowwise) {
+    if (g.a_mode == 4 && k0 >= g.split) {
+      // gathered half of a message-passing layer: 8 channels of one row,
+      // summed over its neighbours in FP32, in neighbour order
+      const int r = tid >> 2, k8 = (tid & 3) * 8;
+      const int m = m0 + r, kc = k0 + k8 - g.split;
+      const uint16_t *h0 = g.A1 + kc;
+      if (m < g.M && k0 + k8 + 8 <= kz1 && !(g.lda1 & 7) && aligned8(h0)) {
+        const uint8_t *nb = g.nbr + (size_t)g.node_atom[m] * kMaxDeg;
+        const int g0 = g.node_g0[m];
+        float acc[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        for (int d = 0; d < kMaxDeg && nb[d] != 0xff; ++d) {
+          uint16_t h[8];
+          unpack8(*reinterpret_cast<const uint4 *>(h0 + (size_t)(g0 + nb[d]) * g.lda1), h);
+#pragma unroll
+          for (int j = 0; j < 8; ++j) acc[j] += bf2f(h[j]);
+        }
+        uint16_t o[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) o[j] = f2bf(acc[j]);
+        const uint4 packed = {(uint32_t)o[0] | ((uint32_t)o[1] << 16), (uint32_t)o[2] | ((uint32_t)o[3] << 16),
+                              (uint32_t)o[4] | ((uint32_t)o[5] << 16), (uint32_t)o[6] | ((uint32_t)o[7] << 16)};
+        *reinterpret_cast<uint4 *>(&As[r][k8]) = packed;
+        if (g.Mout && blockIdx.x == 0) *reinterpret_cast<uint4 *>(g.Mout + (size_t)m * kW + kc) = packed;
+      } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const uint16_t v = (m < g.M && k0 + k8 + j < kz1) ? gemm_a(g, m, k0 + k8 + j) : (uint16_t)0;
+          As[r][k8 + j] = v;
+          if (g.Mout && blockIdx.x == 0 && m < g.M && k0 + k8 + j < kz1) g.Mout[(size_t)m * kW + kc + j] = v;
+        }
+      }
+    } else if (a_rowwise) {
       const int r = tid >> 2, k8 = (tid & 3) * 8;
       const int m = m0 + r, k = k0 + k8;
       const uint16_t *src = a_row8(g, m, k, kz1);
@@ -253,16 +303,6 @@ __global__ void k_gather_x(GraphArgs G, const uint16_t *X, uint16_t *Xmb) {
 }
 
 // M[m] = r(sum over bonded neighbours of H); at most 8 BF16 terms, summed in FP32
-__global__ void k_neighbour_sum(GraphArgs G, const uint16_t *H, uint16_t *M) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (size_t)G.Nn * kW) return;
-  const int m = (int)(i / kW), c = (int)(i % kW);
-  const uint8_t *nb = G.nbr + (size_t)G.node_atom[m] * kMaxDeg;
-  float s = 0.0f;
-  for (int d = 0; d < kMaxDeg && nb[d] != 0xff; ++d) s += bf2f(H[(size_t)(G.node_g0[m] + nb[d]) * kW + c]);
-  M[i] = f2bf(s);
-}
-
 // dP_prev[m] = [H_prev > 0] * r(dHM[m, :128] + sum over neighbours of dHM[., 128:])
 __global__ void k_neighbour_bwd(GraphArgs G, const uint16_t *dHM, const uint16_t *Hprev, uint16_t *dP) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -562,7 +602,7 @@ int alloc_ws(ad_prescreen *ps, int B, int Nn, bool train, MB *mb) {
   const size_t part_floats = std::max(z_nodes * (2 * kW + 1) * kW, z_graphs * (kH + 1) * kH);
   const size_t hsz = al((size_t)Nn * kW * 2);
   size_t sz = al((size_t)Nn * kFeat * 2);
-  sz += (kLayers + 1) * hsz + kLayers * hsz;                        // H, M
+  sz += (kLayers + 1) * hsz + (train ? kLayers * hsz : 0);           // H, M (M: read by the backward pass only)
   sz += al((size_t)B * kW * 2) + 2 * al((size_t)B * kH * 2);        // g z1 z2
   sz += 2 * al((size_t)B * 4);                                       // p dp
   if (train) {
@@ -587,7 +627,7 @@ int alloc_ws(ad_prescreen *ps, int B, int Nn, bool train, MB *mb) {
   mb->Xmb = (uint16_t *)take((size_t)Nn * kFeat * 2);
   for (int l = 0; l <= kLayers; ++l) mb->H[l] = (uint16_t *)take((size_t)Nn * kW * 2);
   mb->M[0] = nullptr;
-  for (int l = 1; l <= kLayers; ++l) mb->M[l] = (uint16_t *)take((size_t)Nn * kW * 2);
+  for (int l = 1; l <= kLayers; ++l) mb->M[l] = train ? (uint16_t *)take((size_t)Nn * kW * 2) : nullptr;
   mb->g = (uint16_t *)take((size_t)B * kW * 2);
   mb->z1 = (uint16_t *)take((size_t)B * kH * 2);
   mb->z2 = (uint16_t *)take((size_t)B * kH * 2);
@@ -655,7 +695,7 @@ hipError_t wgrad(const GemmArgs &gbase, int R, float *part, size_t part_floats, 
   return hipGetLastError();
 }
 
-int forward(ad_prescreen *ps, const ad_batch *b, MB &mb) {
+int forward(ad_prescreen *ps, const ad_batch *b, MB &mb, bool keep_m) {
   ad_ctx *c = ps->ctx;
   hipStream_t s = c->stream;
   const Offs &o = ps->o;
@@ -673,14 +713,17 @@ int forward(ad_prescreen *ps, const ad_batch *b, MB &mb) {
   g.ldc16 = kW;
   PS_TRY(c, gemm(g, s));
   for (int l = 1; l <= kLayers; ++l) {
-    hipLaunchKernelGGL(k_neighbour_sum, dim3(nblk((size_t)mb.Nn * kW)), dim3(256), 0, s, G, mb.H[l - 1], mb.M[l]);
+    // one launch per layer: the neighbour gather runs in the GEMM's A loader
+    // (M = r(A H) is stored only when a backward pass will read it)
     g = gemm_base(mb.Nn, kW, 2 * kW);
-    g.a_mode = 1;
+    g.a_mode = 4;
     g.split = kW;
     g.A1 = mb.H[l - 1];
     g.lda1 = kW;
-    g.A2 = mb.M[l];
-    g.lda2 = kW;
+    g.node_atom = mb.node_atom;
+    g.node_g0 = mb.node_g0;
+    g.nbr = b->ps_nbr;
+    g.Mout = keep_m ? mb.M[l] : nullptr;
     g.B = ps->wbf + o.W[l];
     g.ldb = kW;
     g.bias = ps->w + o.b[l];
@@ -800,7 +843,7 @@ int backward(ad_prescreen *ps, const ad_batch *b, MB &mb) {
 // forward, loss into mb.loss and dL/dp, backward (gradient into ps->gr)
 int step_grad(ad_prescreen *ps, const ad_batch *b, MB &mb) {
   ad_ctx *c = ps->ctx;
-  int rc = forward(ps, b, mb);
+  int rc = forward(ps, b, mb, true);
   if (rc) return rc;
   hipLaunchKernelGGL(k_loss, dim3(1), dim3(256), 0, c->stream, mb.p, mb.y, mb.B, (float)ps->cfg.lam,
                      (float)ps->cfg.tau, mb.loss, mb.dp);
@@ -979,7 +1022,7 @@ extern "C" int ad_prescreen_predict(ad_prescreen *ps, const ad_batch *b, int n, 
   for (int s = 0; s < P.steps(); ++s) {
     bind_step(P, D, s, &mb);
     mb.B = chunk_n[s];
-    rc = forward(ps, b, mb);
+    rc = forward(ps, b, mb, false);
     if (rc) return rc;
     hipLaunchKernelGGL(k_unscale, dim3(nblk(mb.B)), dim3(256), 0, c->stream, mb.p, mb.B, (float)ps->mean,
                        (float)ps->sd, out);
