@@ -590,6 +590,8 @@ def main():
                     help="evaluation cap per run of the stronger judge on one extra holdout")
     ap.add_argument("--max-evals", type=int, default=None,
                     help="override the workload's evaluation cap per run (short profiled runs)")
+    ap.add_argument("--ls-shape", default=None,
+                    help="force the local-search launch shape UNROLL,WG_PER_CU (0 = tuned), e.g. 1,0 for counter passes")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB three times (reference for HBM counters)")
     args = ap.parse_args()
@@ -622,6 +624,9 @@ def main():
         dock = dict(dock, max_evals=args.max_evals)
     log(f"workload {args.workload}: {len(c['ligands'])} ligands generated in {time.time() - t0:.1f}s")
     ctx = pkg.create(synth.forcefield(), 0)
+    if args.ls_shape:
+        u, w = (int(x) for x in args.ls_shape.split(","))
+        ctx.ad_set_launch_shape(u, w)
     t0 = time.time()
     ctx.ad_build_grids(c["grid"], c["receptor"])
     batch = ctx.ad_load_ligands(c["ligands"])

@@ -520,10 +520,16 @@ __device__ double evaluate(const EvalConst &C, const LaneLig<CAP> &LL, EvalLds<C
     rec_b = (STAGE && lane + W < st.n) ? s_pr[lane + W] : pr[lane + W];
     lj_a = STAGE ? s_lj[rec_a.ijt >> 16] : ljt[rec_a.ijt >> 16];
   }
-  // UNROLL (a launch-shape option of the local search) only unrolls the
-  // loop: every lane adds its pairs' energies and forces in the same order
+  // The step count is the same for every lane of the group (the last step
+  // masks the lanes past the list), so step k of every lane is one and the
+  // same instruction whatever the unroll: UNROLL (a launch-shape option of
+  // the local search) then changes neither a lane's order of pairs nor the
+  // order in which the lanes' force additions reach an accumulator.
+  const int n_steps = (L.n_pairs + W - 1) / W;
 #pragma unroll UNROLL
-  for (int p = lane; p < L.n_pairs; p += W) {
+  for (int step = 0; step < n_steps; ++step) {
+    const int p = step * W + lane;
+    if (p >= L.n_pairs) continue;
     const PairRec rec = rec_a;
     const LJRec lj = lj_a;
     rec_a = rec_b;

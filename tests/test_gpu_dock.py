@@ -173,7 +173,12 @@ def test_schedules_give_identical_results(pkg, setup):
     unroll 1 and 2, fewer work-groups per CU) forced and autotuned: bitwise
     the same docking results."""
     ctx, grid, G = setup
-    ligs = [synth.ligand(70 + i, n, t) for i, (n, t) in enumerate([(12, 2), (30, 7), (70, 20), (50, 12), (90, 25)])]
+    # sizes across both buckets and the packing limit; large pair lists make
+    # lanes of different steps add to the same atoms (where an order change
+    # between schedules would show in the last bits)
+    sizes = [(12, 2), (30, 7), (70, 20), (50, 12), (90, 25), (20, 5), (40, 10), (60, 16), (64, 24), (100, 30),
+             (33, 8), (45, 13), (128, 32), (58, 14)]
+    ligs = [synth.ligand(70 + i, n, t) for i, (n, t) in enumerate(sizes)]
     batch = ctx.ad_load_ligands(ligs)
     p = small_params(pkg, ls_iters=30, max_gens=5)
     ref = None
@@ -209,9 +214,9 @@ def test_schedules_give_identical_results(pkg, setup):
         assert not ctx.ad_get_schedule()["graph"]
         assert np.array_equal(r["run_energy"], ref["run_energy"])
         # a subset that holds only the small bucket
-        r2 = ctx.ad_dock_select(batch, np.array([3, 0], np.int32), p, 77, per_run=True)
+        r2 = ctx.ad_dock_select(batch, np.array([3, 0, 13], np.int32), p, 77, per_run=True)
         assert ctx.ad_get_schedule()["stage_pairs"][1] == -1
-        assert np.array_equal(r2["run_energy"], ref["run_energy"][[3, 0]])
+        assert np.array_equal(r2["run_energy"], ref["run_energy"][[3, 0, 13]])
     finally:
         ctx.ad_set_schedule()
         ctx.ad_set_launch_shape(0, 0)
