@@ -279,6 +279,7 @@ def batch_leg(args, log_fn):
     ctx.ad_set_kernel_timing(False)
     sched = ctx.ad_get_schedule()
     shape = ctx.ad_get_launch_shape()
+    queue = ctx.ad_get_work_queue()
     n_ls = int(np.floor(dock["ls_rate"] * dock["pop"] + 0.5))
     ls_flop = dock["nrun"] * n_ls * dock["ls_iters"] * sum(flops_per_eval(i, True) for i in infos)
     ls_ms, ls_n = kt["ls"]
@@ -295,7 +296,7 @@ def batch_leg(args, log_fn):
         "generations": int(r["generations"][0]),
         "buckets": {"le64_atoms": batch.n - big, "le128_atoms": big},
         "ls_stage_pairs": sched["stage_pairs"], "ls_pair_unroll": shape["unroll"], "ls_wg_per_cu": shape["wg_per_cu"],
-        "packed_runs": sched["packed_runs"],
+        "work_queue": queue, "packed_runs": sched["packed_runs"],
         "ls_phase_avg_ms": round(ls_ms / max(ls_n, 1), 3),
         "ls_phase_tflops": round(ls_flop / (ls_ms / 1e3 / max(ls_n, 1)) / 1e12, 3) if ls_n else None,
     }
@@ -592,6 +593,8 @@ def main():
                     help="override the workload's evaluation cap per run (short profiled runs)")
     ap.add_argument("--ls-shape", default=None,
                     help="force the local-search launch shape UNROLL,WG_PER_CU (0 = tuned), e.g. 1,0 for counter passes")
+    ap.add_argument("--work-queue", type=int, default=-1, choices=(-1, 0, 1),
+                    help="persistent work queue of the generation launches: -1 tuned, 0 off, 1 on")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB three times (reference for HBM counters)")
     args = ap.parse_args()
@@ -627,6 +630,7 @@ def main():
     if args.ls_shape:
         u, w = (int(x) for x in args.ls_shape.split(","))
         ctx.ad_set_launch_shape(u, w)
+    ctx.ad_set_work_queue(args.work_queue)
     t0 = time.time()
     ctx.ad_build_grids(c["grid"], c["receptor"])
     batch = ctx.ad_load_ligands(c["ligands"])
@@ -656,6 +660,7 @@ def main():
     ctx.ad_set_kernel_timing(False)
     schedule = ctx.ad_get_schedule()
     shape = ctx.ad_get_launch_shape()
+    queue = ctx.ad_get_work_queue()
     # the same step replayed as a graph (kernel timing off), for comparison
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -728,7 +733,8 @@ def main():
     # score-grad evaluations per second inside the local-search kernel
     out["schedule"] = {"timed_steps": {"graph": schedule["graph"], "ls_stage_pairs": schedule["stage_pairs"],
                                        "packed_runs": schedule["packed_runs"],
-                                       "ls_pair_unroll": shape["unroll"], "ls_wg_per_cu": shape["wg_per_cu"]},
+                                       "ls_pair_unroll": shape["unroll"], "ls_wg_per_cu": shape["wg_per_cu"],
+                                       "work_queue": queue},
                        "graph_replay_ms_per_step": round(graph_ms, 2), "graph": schedule_graph["graph"]}
     out["score_grad_evals_per_s"] = round(dock["nrun"] * n_lig * n_ls * dock["ls_iters"] / ls_avg_s, 1)
     if not args.no_variants:

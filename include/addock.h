@@ -392,6 +392,25 @@ int ad_get_schedule(ad_ctx *ctx, int *stage_pairs, int *graph_used, int *packed_
 int ad_set_launch_shape(ad_ctx *ctx, int unroll, int wg_per_cu);
 int ad_get_launch_shape(ad_ctx *ctx, int *unroll, int *wg_per_cu);
 
+/* Persistent work queue of the generation launches (the batching of many
+ * uneven ligands, Sec. 2.2: one launch per generation covers every run of
+ * every ligand of a bucket).  Off, every work-group of a GA or local-search
+ * launch computes one item (an individual of a run; a local search).  On,
+ * each launch takes about as many work-groups as the device keeps resident
+ * and they take items in run order (longest first) from a per-generation
+ * ticket counter until none is left; items of runs that have stopped
+ * (autostop, Solis-Wets) are skipped without a dispatch.  Results are
+ * bitwise the same either way.  mode: -1 the autotuner times the ADADELTA
+ * local search both ways and keeps the queue only if it is 3 % faster (the
+ * default), 0 off, 1 on; the GA launches follow the bucket's choice (with
+ * Solis-Wets, whose launches stay one work-group per item, they follow a
+ * forced 1).  The ticket counters live in the docking state and are cleared
+ * once per dock call, before any launch.  ad_get_work_queue: used[2], the
+ * mode per bucket (<= 64, <= 128 atoms) of the last dock call (-1: bucket
+ * empty).  AD_E_INVALID for a mode out of range. */
+int ad_set_work_queue(ad_ctx *ctx, int mode);
+int ad_get_work_queue(ad_ctx *ctx, int *used);
+
 /* ---- diagnostics ----------------------------------------------------------
  * Kernel timing with HIP events recorded on the context's stream around
  * every launch of the docking and scoring kernels, for throughput and

@@ -32,7 +32,7 @@ EXPORTS = ["ad_create", "ad_destroy", "ad_last_error", "ad_set_stream", "ad_sync
            "ad_build_grids", "ad_grid_check", "ad_ligand_check", "ad_load_ligands", "ad_load_ligands_packed", "ad_free_batch", "ad_dock_stream", "ad_batch_info",
            "ad_score_poses", "ad_score_poses_shape", "ad_score_poses_noalloc", "ad_dock_batch", "ad_dock_select", "ad_local_search", "ad_local_search_shape", "ad_solis_wets", "ad_initial_population",
            "ad_set_kernel_timing", "ad_get_kernel_timing", "ad_set_schedule", "ad_get_schedule", "ad_set_launch_shape",
-           "ad_get_launch_shape",
+           "ad_get_launch_shape", "ad_set_work_queue", "ad_get_work_queue",
            "ad_prescreen_n_params", "ad_prescreen_create",
            "ad_prescreen_destroy", "ad_prescreen_set_params", "ad_prescreen_get_params", "ad_prescreen_set_scale",
            "ad_prescreen_get_scale", "ad_prescreen_predict", "ad_prescreen_grad", "ad_prescreen_train"]
@@ -170,6 +170,8 @@ def lib():
     L.ad_get_schedule.argtypes = [vp, ip, ip, ip]
     L.ad_set_launch_shape.argtypes = [vp, C.c_int, C.c_int]
     L.ad_get_launch_shape.argtypes = [vp, ip, ip]
+    L.ad_set_work_queue.argtypes = [vp, C.c_int]
+    L.ad_get_work_queue.argtypes = [vp, ip]
     L.ad_prescreen_n_params.argtypes = []
     L.ad_prescreen_create.argtypes = [vp, C.POINTER(PrescreenCfg), C.c_uint64, C.POINTER(vp)]
     L.ad_prescreen_destroy.argtypes = [vp]
@@ -373,6 +375,15 @@ class Context:
         u, w = (C.c_int * 2)(), (C.c_int * 2)()
         self._check(lib().ad_get_launch_shape(self.h, u, w))
         return dict(unroll=[u[0], u[1]], wg_per_cu=[w[0], w[1]])
+
+    def ad_set_work_queue(self, mode=-1):
+        """Persistent work queue of the generation launches: -1 tuned, 0 off, 1 on."""
+        self._check(lib().ad_set_work_queue(self.h, int(mode)))
+
+    def ad_get_work_queue(self):
+        q = (C.c_int * 2)()
+        self._check(lib().ad_get_work_queue(self.h, q))
+        return [q[0], q[1]]
 
     def ad_synchronize(self):
         self._check(lib().ad_synchronize(self.h))

@@ -51,6 +51,11 @@ struct DockArgs {
   // pair-loop unroll (1 or 2) and extra dynamic LDS per work-group that caps
   // the work-groups resident per CU (0: as many as the kernel's LDS allows)
   int ls_unroll, ls_pad;
+  // persistent work queue (null: one work-group per item): per-generation
+  // ticket counters of the GA and local-search launches (index = generation,
+  // zero when the docking call starts) and the grids their launches take
+  unsigned int *q_ga, *q_ls;
+  int q_grid_ga, q_grid_ls;
   // Solis-Wets local search
   int ls_method;     // 0 ADADELTA, 1 Solis-Wets
   float sw_rho, sw_rho_lb, sw_sig_t, sw_sig_ang;
@@ -78,6 +83,10 @@ size_t ls_dynamic_lds(const EvalConst &C, const DockArgs &D);
 // LDS of one local-search work-group of the bucket (static + dynamic, pad
 // excluded): the tuner sizes its occupancy candidates from it
 size_t ls_workgroup_lds(const EvalConst &C, int cap, const DockArgs &D);
+// work-groups of the bucket's GA (kind 0) or local-search (kind 1) kernel
+// that the current device keeps resident at once, for D's launch shape: the
+// grid of a queued launch
+int queue_grid(const EvalConst &C, int cap, const DockArgs &D, int kind);
 hipError_t launch_dock_finalize(const DockArgs &D, int buf, float *best_E, float *best_G, hipStream_t s);
 hipError_t launch_run_status(const DockArgs &D, int gen, hipStream_t s);
 hipError_t launch_solis_wets(const EvalConst &C, int cap, const DockArgs &D, int n, const int *lig_idx, float *geno,
@@ -134,9 +143,9 @@ struct ad_batch {
 };
 
 // a bucket's local-search schedule: staged pair records, pair-loop unroll,
-// work-groups resident per CU
+// work-groups resident per CU, persistent work queue
 struct LsChoice {
-  int stage = 0, unroll = 1, wg_per_cu = 0;
+  int stage = 0, unroll = 1, wg_per_cu = 0, queue = 0;
 };
 
 struct ad_ctx {
@@ -188,8 +197,9 @@ struct ad_ctx {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   std::map<std::vector<int64_t>, LsChoice> tune_cache;
   int forced_unroll = 0, forced_wgcu = 0;   // 0: tuned
+  int forced_queue = -1;                     // -1: tuned, 0 off, 1 on
   int last_stage[2] = {-1, -1};
-  int last_unroll[2] = {-1, -1}, last_wgcu[2] = {-1, -1};
+  int last_unroll[2] = {-1, -1}, last_wgcu[2] = {-1, -1}, last_queue[2] = {-1, -1};
   int last_graph = 0;
   int last_packed = 0;      // runs of the last dock call packed two individuals per wavefront
   uint64_t next_batch_uid = 1;

@@ -129,15 +129,17 @@ int choose_schedule(ad_ctx *c, const ad_batch *b, const int *sel, int n_lig, con
   if (c->forced_stage >= 0)
     for (int ns : stage_cand)
       if (ns <= c->forced_stage) best.stage = ns;
+  best.queue = c->forced_queue > 0 ? 1 : 0;
   const bool tune_shape = c->autotune && (c->forced_unroll <= 0 || c->forced_wgcu <= 0);
   const bool tune_stage = c->autotune && c->forced_stage < 0 && stage_cand.size() > 1;
-  if (!tune_shape && !tune_stage) {
+  const bool tune_queue = c->autotune && c->forced_queue < 0;
+  if (!tune_shape && !tune_stage && !tune_queue) {
     if (best.wg_per_cu <= 0) best.wg_per_cu = natural;
     *out = best;
     return AD_OK;
   }
   std::vector<int64_t> key = {(int64_t)b->uid, cap, Dk.pop, Dk.n_ls, Dk.n_launch, n_lig, Dk.n_dual,
-                              c->forced_unroll, c->forced_wgcu, c->forced_stage};
+                              c->forced_unroll, c->forced_wgcu, c->forced_stage, c->forced_queue};
   if (sel) {
     uint64_t h = 1469598103934665603ull;
     for (int l = 0; l < n_lig; ++l) h = (h ^ (uint64_t)sel[l]) * 1099511628211ull;
@@ -156,7 +158,8 @@ int choose_schedule(ad_ctx *c, const ad_batch *b, const int *sel, int n_lig, con
   const size_t sz_e = align256(pop_floats * sizeof(float));
   const size_t sz_v = align256((size_t)Dk.n_runs * sizeof(unsigned long long));
   const size_t sz_o = align256((size_t)Dk.n_launch * sizeof(int));
-  char *blk = (char *)c->scratch_alloc(sz_g + sz_e + sz_v + sz_o, 3);
+  const size_t sz_q = 256;
+  char *blk = (char *)c->scratch_alloc(sz_g + sz_e + sz_v + sz_o + sz_q, 3);
   if (!blk) return c->fail(AD_E_OOM, "cannot allocate autotuning buffers");
   std::vector<int> host_order(Dk.n_launch), sample;
   HIP_TRY(c, hipMemcpyAsync(host_order.data(), Dk.run_order, Dk.n_launch * sizeof(int), hipMemcpyDeviceToHost,
@@ -176,7 +179,9 @@ int choose_schedule(ad_ctx *c, const ad_batch *b, const int *sel, int n_lig, con
   T.energy = (float *)(blk + sz_g);
   T.evals = (unsigned long long *)(blk + sz_g + sz_e);
   int *d_sample = (int *)(blk + sz_g + sz_e + sz_v);
+  unsigned int *d_q = (unsigned int *)(blk + sz_g + sz_e + sz_v + sz_o);
   T.run_order = d_sample;
+  T.q_ga = nullptr;
   T.n_launch = (int)sample.size();
   T.ls_iters = std::min(Dk.ls_iters, 24);
   HIP_TRY(c, hipMemcpyAsync(d_sample, sample.data(), sample.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
@@ -188,10 +193,13 @@ int choose_schedule(ad_ctx *c, const ad_batch *b, const int *sel, int n_lig, con
     T.stage_pairs = ch.stage;
     T.ls_unroll = ch.unroll;
     T.ls_pad = pad_for(ls_workgroup_lds(C, cap, T), ch.wg_per_cu);
+    T.q_ls = ch.queue ? d_q : nullptr;
+    T.q_grid_ls = ch.queue ? queue_grid(C, cap, T, 1) : 0;
     float ms_min = INFINITY;
     for (int rep = 0; rep < 3 && rc == AD_OK; ++rep) {
       hipError_t e = hipMemcpyAsync(T.geno, Dk.geno, pop_floats * kStride * sizeof(float), hipMemcpyDeviceToDevice,
                                     c->stream);
+      if (e == hipSuccess && ch.queue) e = hipMemsetAsync(d_q, 0, sizeof(unsigned int), c->stream);
       if (e == hipSuccess)
         e = hipMemcpyAsync(T.energy, Dk.energy, pop_floats * sizeof(float), hipMemcpyDeviceToDevice, c->stream);
       if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
@@ -227,6 +235,18 @@ int choose_schedule(ad_ctx *c, const ad_batch *b, const int *sel, int n_lig, con
           best = ch;
         }
       }
+  }
+  if (tune_queue && rc == AD_OK) {
+    // the persistent work queue against one work-group per item, with the
+    // shape chosen so far
+    LsChoice ch = best;
+    ch.queue = 1 - best.queue;
+    float ms;
+    time_ms(ch, &ms);
+    if (rc == AD_OK && ms < 0.97f * best_ms) {
+      best_ms = ms;
+      best = ch;
+    }
   }
   if (tune_stage && rc == AD_OK) {
     // staged records run the plain (unroll 1) loop; a larger staging size
@@ -314,8 +334,10 @@ int dock_impl(ad_ctx *c, const ad_batch *b, int n_lig, const int *sel, const ad_
   const size_t sz_lgen = per_run ? align256((size_t)n_runs * sizeof(int)) : 0;
   const size_t sz_hist = per_run ? align256((size_t)n_runs * 10 * sizeof(float)) : 0;
   const size_t sz_nact = per_run ? align256((size_t)(G + 1) * sizeof(int)) : 0;
+  // work-queue tickets: [bucket][GA, local search][generation 0..G]
+  const size_t sz_q = align256((size_t)4 * (G + 1) * sizeof(unsigned int));
   const size_t total = sz_geno + sz_E + sz_ev + sz_ord + sz_id + sz_bE + sz_bG + sz_lG + sz_lE + sz_lT + sz_li +
-                       sz_map + sz_rl + sz_act + sz_lgen + sz_hist + sz_nact;
+                       sz_map + sz_rl + sz_act + sz_lgen + sz_hist + sz_nact + sz_q;
   hipSetDevice(c->device);
   if (c->dock_bytes < total) {
     hipStreamSynchronize(c->stream);
@@ -350,6 +372,7 @@ int dock_impl(ad_ctx *c, const ad_batch *b, int n_lig, const int *sel, const ad_
   D.last_gen = per_run ? (int *)carve(sz_lgen) : nullptr;
   D.hist = per_run ? (float *)carve(sz_hist) : nullptr;
   D.n_active = per_run ? (int *)carve(sz_nact) : nullptr;
+  unsigned int *d_q = (unsigned int *)carve(sz_q);
   D.run_order = d_order;
   D.n_dual = 0;
   D.lig_id = d_id;
@@ -445,25 +468,43 @@ int dock_impl(ad_ctx *c, const ad_batch *b, int n_lig, const int *sel, const ad_
     c->timing_end(0, t0);
   }
   const bool do_ls = n_ls > 0 && p->ls_iters > 0;
+  HIP_TRY(c, hipMemsetAsync(d_q, 0, sz_q, c->stream));
   for (int bk = 0; bk < 2; ++bk) {
     c->last_stage[bk] = -1;
     c->last_unroll[bk] = -1;
     c->last_wgcu[bk] = -1;
-    if (!Db[bk].n_launch || !do_ls) continue;
-    if (p->ls_method == 1) {   // Solis-Wets: its own kernel, one fixed shape
+    c->last_queue[bk] = -1;
+    if (!Db[bk].n_launch) continue;
+    const int cap_b = bk ? 128 : 64;
+    // the GA launches take the bucket's queue mode: the local search's
+    // (tuned or forced) under ADADELTA, else the forced one
+    int queue = c->forced_queue > 0 ? 1 : 0;
+    if (do_ls && p->ls_method == 1) {   // Solis-Wets: its own kernel, one fixed shape
       c->last_stage[bk] = 0;
-      continue;
+    } else if (do_ls) {
+      // packed runs stage no pairs; their launch still takes the tuned shape
+      LsChoice ch;
+      rc = choose_schedule(c, b, sel, n_lig, C, Db[bk], cap_b, max_pairs[bk], Db[bk].n_dual == 0, &ch);
+      if (rc) return rc;
+      Db[bk].stage_pairs = ch.stage;
+      Db[bk].ls_unroll = ch.unroll;
+      Db[bk].ls_pad = pad_for(ls_workgroup_lds(C, cap_b, Db[bk]), ch.wg_per_cu);
+      c->last_stage[bk] = ch.stage;
+      c->last_unroll[bk] = ch.unroll;
+      c->last_wgcu[bk] = ch.wg_per_cu;
+      queue = ch.queue;
+      if (queue) {
+        Db[bk].q_ls = d_q + (size_t)(2 * bk + 1) * (G + 1);
+        Db[bk].q_grid_ls = queue_grid(C, cap_b, Db[bk], 1);
+        if (Db[bk].q_grid_ls <= 0) return c->fail(AD_E_HIP, "cannot size the work-queue grid");
+      }
     }
-    // packed runs stage no pairs; their launch still takes the tuned shape
-    LsChoice ch;
-    rc = choose_schedule(c, b, sel, n_lig, C, Db[bk], bk ? 128 : 64, max_pairs[bk], Db[bk].n_dual == 0, &ch);
-    if (rc) return rc;
-    Db[bk].stage_pairs = ch.stage;
-    Db[bk].ls_unroll = ch.unroll;
-    Db[bk].ls_pad = pad_for(ls_workgroup_lds(C, bk ? 128 : 64, Db[bk]), ch.wg_per_cu);
-    c->last_stage[bk] = ch.stage;
-    c->last_unroll[bk] = ch.unroll;
-    c->last_wgcu[bk] = ch.wg_per_cu;
+    if (queue) {
+      Db[bk].q_ga = d_q + (size_t)(2 * bk) * (G + 1);
+      Db[bk].q_grid_ga = queue_grid(C, cap_b, Db[bk], 0);
+      if (Db[bk].q_grid_ga <= 0) return c->fail(AD_E_HIP, "cannot size the work-queue grid");
+    }
+    c->last_queue[bk] = queue;
   }
 
   // the generation loop: bucket 0 on the context's stream, bucket 1 on the
@@ -716,6 +757,20 @@ extern "C" int ad_get_launch_shape(ad_ctx *c, int *unroll, int *wg_per_cu) {
     if (unroll) unroll[bk] = c->last_unroll[bk];
     if (wg_per_cu) wg_per_cu[bk] = c->last_wgcu[bk];
   }
+  return AD_OK;
+}
+
+extern "C" int ad_set_work_queue(ad_ctx *c, int mode) {
+  if (!c) return AD_E_INVALID;
+  if (mode < -1 || mode > 1) return c->fail(AD_E_INVALID, "work queue: -1 (tune), 0 (off) or 1 (on)");
+  c->forced_queue = mode;
+  return AD_OK;
+}
+
+extern "C" int ad_get_work_queue(ad_ctx *c, int *used) {
+  if (!c) return AD_E_INVALID;
+  if (used)
+    for (int bk = 0; bk < 2; ++bk) used[bk] = c->last_queue[bk];
   return AD_OK;
 }
 

@@ -933,16 +933,34 @@ __device__ __forceinline__ int tournament(const float *E, int pop, double tour_p
   return unif(w2) < tour_p ? better : worse;
 }
 
-// One GA generation `gen` (>= 1): individual 0 keeps the previous best,
-// the others are tournament / crossover / mutation children, evaluated.
+// Work queue of a generation launch.  Without a queue every work-group
+// computes one item (the item is its block index).  With a queue (D.q_ga /
+// D.q_ls set) the grid holds about as many work-groups as the device keeps
+// resident, and each one takes the next item, or chunk of items, from the
+// launch's counter (one per generation, zero at the start of the docking
+// call) until the counter passes the item count.  Items are taken in item
+// order, so the run order's longest-first ranking still decides what starts
+// first, and items of stopped runs are skipped without a dispatch.  What an
+// item computes does not depend on the work-group that takes it: results
+// are bitwise the same with and without the queue.
+__device__ __forceinline__ int next_ticket(unsigned int *ctr) {
+  int t = 0;
+  if (threadIdx.x == 0) t = (int)atomicAdd(ctr, 1u);
+  return __builtin_amdgcn_readfirstlane(t);
+}
+
+// GA items taken per ticket: the counter is hit once per chunk
+constexpr int kGaChunk = 16;
+
+// One GA generation `gen` (>= 1), item = run slot * pop + individual:
+// individual 0 keeps the previous best, the others are tournament /
+// crossover / mutation children, evaluated.
 template <int CAP>
-__global__ __launch_bounds__(64) void k_ga_generation(EvalConst C, DockArgs D, int gen) {
-  __shared__ EvalLds<CAP> S;
-  init_eval_lds(S, threadIdx.x);
+__device__ __forceinline__ void ga_item(const EvalConst &C, const DockArgs &D, int gen, int item, EvalLds<CAP> &S) {
   const int lane = threadIdx.x;
-  const int R = D.run_order[blockIdx.x / D.pop];
+  const int R = D.run_order[item / D.pop];
   if (D.active && !D.active[R]) return;   // the run has stopped
-  const int i = blockIdx.x % D.pop;
+  const int i = item % D.pop;
   const int li = R / D.nrun, run = R % D.nrun;
   const int src = (gen - 1) & 1, dst = gen & 1;
   const float *oldG = D.geno + pop_off(D, src, R) * kStride;
@@ -1009,6 +1027,24 @@ __global__ __launch_bounds__(64) void k_ga_generation(EvalConst C, DockArgs D, i
   }
 }
 
+template <int CAP, bool QUEUE>
+__global__ __launch_bounds__(64) void k_ga_generation(EvalConst C, DockArgs D, int gen) {
+  __shared__ EvalLds<CAP> S;
+  init_eval_lds(S, threadIdx.x);
+  if (!QUEUE) {
+    ga_item<CAP>(C, D, gen, (int)blockIdx.x, S);
+    return;
+  }
+  const int n_items = D.n_launch * D.pop;
+  for (int t = next_ticket(D.q_ga + gen); t * kGaChunk < n_items; t = next_ticket(D.q_ga + gen)) {
+    const int end = min(n_items, (t + 1) * kGaChunk);
+    for (int item = t * kGaChunk; item < end; ++item) {
+      ga_item<CAP>(C, D, gen, item, S);
+      __syncthreads();
+    }
+  }
+}
+
 // ADADELTA for small ligands (at most kDualAtoms atoms and kDualTor
 // torsions): two individuals per wavefront, one per half of 32 lanes
 // (atoms, torsions and degrees of freedom on lanes, pairs strided by 32),
@@ -1021,7 +1057,8 @@ __global__ __launch_bounds__(64) void k_ga_generation(EvalConst C, DockArgs D, i
 // packed work-groups; dynamic LDS: 2 * pop ints (each half's pick
 // permutation).
 template <int UNROLL>
-__device__ void ls_dual(const EvalConst &C, const DockArgs &D, int gen, int wg, EvalLds<kDualAtoms, kDualTor> *S2) {
+__device__ __forceinline__ void ls_dual(const EvalConst &C, const DockArgs &D, int gen, int wg,
+                                        EvalLds<kDualAtoms, kDualTor> *S2) {
   extern __shared__ __attribute__((aligned(16))) char dyn_lds[];
   const int half = threadIdx.x >> 5, lane = threadIdx.x & 31;
   EvalLds<kDualAtoms, kDualTor> &S = S2[half];
@@ -1037,6 +1074,7 @@ __device__ void ls_dual(const EvalConst &C, const DockArgs &D, int gen, int wg, 
   const int slot = live ? k - run_slot * D.n_ls : 0;
   const int R = D.run_order[chunk * D.nrun + run_slot];
   if (D.active && !D.active[R]) live = false;
+  if (__ballot(live) == 0) return;   // both halves idle (stopped runs): nothing to compute
   const int run = R % D.nrun;
   const int m = D.pop - 1;
   for (int j = lane; j < m; j += 32) perm[j] = j + 1;
@@ -1063,31 +1101,21 @@ __device__ void ls_dual(const EvalConst &C, const DockArgs &D, int gen, int wg, 
 
 // ADADELTA on the individuals picked for generation `gen`: n_ls distinct
 // indices from 1..pop-1 by a partial Fisher-Yates shuffle (word s of the
-// pick stream draws the partner of position s).  Dynamic LDS: pop ints.
+// pick stream draws the partner of position s).  Item = run slot * n_ls +
+// pick, over the bucket's one-wavefront runs (those after the packed ones).
 // With STAGE the first D.stage_pairs pair records of the ligand and the
 // type-pair table are copied to LDS once and read from there by all
 // ls_iters evaluations (the results are bitwise the same either way).
 // Dynamic LDS: pop ints (the pick permutation), then the staged records.
-template <int CAP, bool STAGE, int UNROLL = 1>
-__global__ __launch_bounds__(64) void k_ls_generation(EvalConst C, DockArgs D, int gen) {
-  // the 64-atom variant without staging also runs the packed work-groups
-  // (ls_dual), after the others; both share one static LDS block
-  constexpr bool kPack = CAP == 64 && !STAGE;
-  constexpr size_t kOne = sizeof(EvalLds<CAP>), kTwo = 2 * sizeof(EvalLds<kDualAtoms, kDualTor>);
-  __shared__ __attribute__((aligned(16))) char lds[kPack && kTwo > kOne ? kTwo : kOne];
-  const int n_single = (D.n_launch - D.n_dual) * D.n_ls;
-  if (kPack && (int)blockIdx.x >= n_single) {
-    ls_dual<UNROLL>(C, D, gen, (int)blockIdx.x - n_single, reinterpret_cast<EvalLds<kDualAtoms, kDualTor> *>(lds));
-    return;
-  }
-  EvalLds<CAP> &S = *reinterpret_cast<EvalLds<CAP> *>(lds);
-  init_eval_lds(S, threadIdx.x);
+template <int CAP, bool STAGE, int UNROLL>
+__device__ __forceinline__ void ls_single(const EvalConst &C, const DockArgs &D, int gen, int item, EvalLds<CAP> &S) {
   extern __shared__ __attribute__((aligned(16))) char dyn_lds[];
   int *perm = reinterpret_cast<int *>(dyn_lds);
   const int lane = threadIdx.x;
-  const int R = D.run_order[D.n_dual + blockIdx.x / D.n_ls];
+  const int R = D.run_order[D.n_dual + item / D.n_ls];
   if (D.active && !D.active[R]) return;
-  const int slot = blockIdx.x % D.n_ls;
+  init_eval_lds(S, lane);
+  const int slot = item % D.n_ls;
   const int li = R / D.nrun, run = R % D.nrun;
   const int m = D.pop - 1;
   for (int j = lane; j < m; j += 64) perm[j] = j + 1;
@@ -1121,6 +1149,32 @@ __global__ __launch_bounds__(64) void k_ls_generation(EvalConst C, DockArgs D, i
   adadelta_wave<CAP, STAGE, 64, kMaxTor, UNROLL>(C, LL, S, lane, D.geno + off * kStride, D.energy + off, D.ls_iters,
                                                  D.rho, D.eps, st);
   if (lane == 0) atomicAdd(&D.evals[R], (unsigned long long)D.ls_iters);
+}
+
+// One launch covers the bucket's one-wavefront items, then (64-atom variant
+// without staging) the packed work-groups of ls_dual, one item each; both
+// kinds share one static LDS block.
+template <int CAP, bool STAGE, int UNROLL = 1, bool QUEUE = false>
+__global__ __launch_bounds__(64) void k_ls_generation(EvalConst C, DockArgs D, int gen) {
+  constexpr bool kPack = CAP == 64 && !STAGE;
+  constexpr size_t kOne = sizeof(EvalLds<CAP>), kTwo = 2 * sizeof(EvalLds<kDualAtoms, kDualTor>);
+  __shared__ __attribute__((aligned(16))) char lds[kPack && kTwo > kOne ? kTwo : kOne];
+  const int n_single = (D.n_launch - D.n_dual) * D.n_ls;
+  auto run_item = [&](int item) {
+    if (kPack && item >= n_single)
+      ls_dual<UNROLL>(C, D, gen, item - n_single, reinterpret_cast<EvalLds<kDualAtoms, kDualTor> *>(lds));
+    else
+      ls_single<CAP, STAGE, UNROLL>(C, D, gen, item, *reinterpret_cast<EvalLds<CAP> *>(lds));
+  };
+  if (!QUEUE) {
+    run_item((int)blockIdx.x);
+    return;
+  }
+  const int n_items = n_single + (kPack ? (D.n_dual / D.nrun) * ((D.nrun * D.n_ls + 1) / 2) : 0);
+  for (int t = next_ticket(D.q_ls + gen); t < n_items; t = next_ticket(D.q_ls + gen)) {
+    run_item(t);
+    __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1552,9 +1606,16 @@ hipError_t launch_dock_init(const EvalConst &C, int cap, const DockArgs &D, hipS
 
 hipError_t launch_ga_generation(const EvalConst &C, int cap, const DockArgs &D, int gen, hipStream_t s) {
   if (D.n_launch <= 0) return hipSuccess;
+  if (D.q_ga) {
+    const long long chunks = ((long long)D.n_launch * D.pop + kGaChunk - 1) / kGaChunk;
+    const dim3 grid((unsigned)std::max(1LL, std::min(chunks, (long long)D.q_grid_ga)));
+    if (cap <= 64) hipLaunchKernelGGL((k_ga_generation<64, true>), grid, dim3(64), 0, s, C, D, gen);
+    else hipLaunchKernelGGL((k_ga_generation<128, true>), grid, dim3(64), 0, s, C, D, gen);
+    return hipGetLastError();
+  }
   return for_run_chunks(D, D.pop, [&](const DockArgs &Dc, dim3 grid) {
-    if (cap <= 64) hipLaunchKernelGGL((k_ga_generation<64>), grid, dim3(64), 0, s, C, Dc, gen);
-    else hipLaunchKernelGGL((k_ga_generation<128>), grid, dim3(64), 0, s, C, Dc, gen);
+    if (cap <= 64) hipLaunchKernelGGL((k_ga_generation<64, false>), grid, dim3(64), 0, s, C, Dc, gen);
+    else hipLaunchKernelGGL((k_ga_generation<128, false>), grid, dim3(64), 0, s, C, Dc, gen);
   });
 }
 
@@ -1573,17 +1634,78 @@ size_t ls_workgroup_lds(const EvalConst &C, int cap, const DockArgs &D) {
   return sizeof(EvalLds<128>) + ls_dynamic_lds(C, D);
 }
 
-// the local-search kernel of a bucket with the launch shape's pair-loop unroll
-template <int CAP, bool STAGE>
-void launch_ls_kernel(int unroll, dim3 grid, size_t dyn, hipStream_t s, const EvalConst &C, const DockArgs &D,
-                      int gen) {
-  if constexpr (!STAGE) {   // staged pair records keep the plain loop
+// the local-search kernel of a bucket with the launch shape's pair-loop
+// unroll, queued (D.q_ls set) or one work-group per item
+template <int CAP, bool STAGE, bool QUEUE>
+const void *ls_kernel_ptr(int unroll) {
+  if constexpr (!STAGE)   // staged pair records keep the plain loop
+    if (unroll == 2) return reinterpret_cast<const void *>(&k_ls_generation<CAP, false, 2, QUEUE>);
+  return reinterpret_cast<const void *>(&k_ls_generation<CAP, STAGE, 1, QUEUE>);
+}
+
+template <int CAP, bool STAGE, bool QUEUE>
+void launch_ls_variant(int unroll, dim3 grid, size_t dyn, hipStream_t s, const EvalConst &C, const DockArgs &D,
+                       int gen) {
+  if constexpr (!STAGE) {
     if (unroll == 2) {
-      hipLaunchKernelGGL((k_ls_generation<CAP, false, 2>), grid, dim3(64), dyn, s, C, D, gen);
+      hipLaunchKernelGGL((k_ls_generation<CAP, false, 2, QUEUE>), grid, dim3(64), dyn, s, C, D, gen);
       return;
     }
   }
-  hipLaunchKernelGGL((k_ls_generation<CAP, STAGE, 1>), grid, dim3(64), dyn, s, C, D, gen);
+  hipLaunchKernelGGL((k_ls_generation<CAP, STAGE, 1, QUEUE>), grid, dim3(64), dyn, s, C, D, gen);
+}
+
+template <int CAP, bool STAGE>
+void launch_ls_kernel(int unroll, dim3 grid, size_t dyn, hipStream_t s, const EvalConst &C, const DockArgs &D,
+                      int gen) {
+  if (D.q_ls) launch_ls_variant<CAP, STAGE, true>(unroll, grid, dyn, s, C, D, gen);
+  else launch_ls_variant<CAP, STAGE, false>(unroll, grid, dyn, s, C, D, gen);
+}
+
+// the bucket's ADADELTA local-search launch: packed work-groups in it, its
+// dynamic LDS (with the occupancy pad) and its item count
+struct LsLaunch {
+  bool packed, stage;
+  size_t dyn;
+  long long n_items;
+};
+LsLaunch ls_launch_of(const EvalConst &C, int cap, const DockArgs &D) {
+  LsLaunch L;
+  const size_t pad = (size_t)std::max(0, D.ls_pad);
+  L.packed = cap <= 64 && D.n_dual > 0 && D.stage_pairs <= 0;
+  L.stage = D.stage_pairs > 0;
+  if (L.packed) {
+    L.dyn = 2 * (size_t)D.pop * sizeof(int) + pad;
+    L.n_items = (long long)(D.n_launch - D.n_dual) * D.n_ls + (long long)(D.n_dual / D.nrun) * ((D.nrun * D.n_ls + 1) / 2);
+  } else {
+    DockArgs t = D;
+    t.n_dual = 0;
+    L.dyn = ls_dynamic_lds(C, t) + pad;
+    L.n_items = (long long)D.n_launch * D.n_ls;
+  }
+  return L;
+}
+
+int queue_grid(const EvalConst &C, int cap, const DockArgs &D, int kind) {
+  int dev = 0, n_cu = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  const void *k;
+  size_t dyn = 0;
+  if (kind == 0) {
+    k = cap <= 64 ? reinterpret_cast<const void *>(&k_ga_generation<64, true>)
+                  : reinterpret_cast<const void *>(&k_ga_generation<128, true>);
+  } else {
+    const LsLaunch L = ls_launch_of(C, cap, D);
+    dyn = L.dyn;
+    if (cap <= 64)
+      k = L.stage ? ls_kernel_ptr<64, true, true>(D.ls_unroll) : ls_kernel_ptr<64, false, true>(D.ls_unroll);
+    else
+      k = L.stage ? ls_kernel_ptr<128, true, true>(D.ls_unroll) : ls_kernel_ptr<128, false, true>(D.ls_unroll);
+  }
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 64, dyn) != hipSuccess) return 0;
+  return std::max(1, n_cu) * std::max(1, per_cu);
 }
 
 hipError_t launch_ls_generation(const EvalConst &C, int cap, const DockArgs &D0, int gen, hipStream_t s) {
@@ -1592,6 +1714,22 @@ hipError_t launch_ls_generation(const EvalConst &C, int cap, const DockArgs &D0,
   DockArgs D = D0;
   const size_t pad = D0.ls_method == 0 ? (size_t)std::max(0, D0.ls_pad) : 0;
   const int ur = D0.ls_unroll;
+  if (D0.q_ls && D0.ls_method == 0) {
+    // persistent work-groups over every item of the bucket (queue)
+    const LsLaunch L = ls_launch_of(C, cap, D0);
+    const dim3 grid((unsigned)std::max(1LL, std::min(L.n_items, (long long)D0.q_grid_ls)));
+    DockArgs Dq = D0;
+    if (!L.packed) Dq.n_dual = 0;
+    if (cap <= 64) {
+      if (L.stage) launch_ls_kernel<64, true>(ur, grid, L.dyn, s, C, Dq, gen);
+      else launch_ls_kernel<64, false>(ur, grid, L.dyn, s, C, Dq, gen);
+    } else {
+      if (L.stage) launch_ls_kernel<128, true>(ur, grid, L.dyn, s, C, Dq, gen);
+      else launch_ls_kernel<128, false>(ur, grid, L.dyn, s, C, Dq, gen);
+    }
+    return hipGetLastError();
+  }
+  D.q_ls = nullptr;
   if (cap <= 64 && D0.ls_method == 0 && D0.n_dual > 0 && D0.stage_pairs <= 0) {
     // packed ligands: ceil(nrun * n_ls / 2) work-groups per ligand, after the
     // single-individual ones in the same launch when the grid allows

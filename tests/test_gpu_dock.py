@@ -207,6 +207,24 @@ def test_schedules_give_identical_results(pkg, setup):
             for k in ("run_energy", "run_genotype", "evals", "best_score"):
                 assert np.array_equal(r[k], ref[k]), (unroll, wgcu, autotune, shape, k)
         ctx.ad_set_launch_shape(0, 0)
+        # the persistent work queue (GA and local search), with other shapes
+        # and staging, eager and as a graph
+        for unroll, wgcu, stage, use_graph in [(1, 0, 0, True), (2, 8, 0, True), (1, 0, 256, False), (2, 0, 0, False)]:
+            ctx.ad_set_schedule(use_graph, False, stage)
+            ctx.ad_set_launch_shape(unroll, wgcu)
+            ctx.ad_set_work_queue(1)
+            r = ctx.ad_dock_batch(batch, p, 77, per_run=True)
+            assert ctx.ad_get_work_queue() == [1, 1]
+            assert ctx.ad_get_schedule()["graph"] == use_graph
+            for k in ("run_energy", "run_genotype", "evals", "best_score"):
+                assert np.array_equal(r[k], ref[k]), ("queue", unroll, wgcu, stage, use_graph, k)
+        ctx.ad_set_work_queue(0)
+        ctx.ad_set_schedule()
+        ctx.ad_set_launch_shape(0, 0)
+        r = ctx.ad_dock_batch(batch, p, 77, per_run=True)
+        assert ctx.ad_get_work_queue() == [0, 0]
+        assert np.array_equal(r["run_energy"], ref["run_energy"])
+        ctx.ad_set_work_queue(-1)
         # kernel timing runs the loop eagerly, with the same results
         ctx.ad_set_kernel_timing(True)
         r = ctx.ad_dock_batch(batch, p, 77, per_run=True)
@@ -220,6 +238,34 @@ def test_schedules_give_identical_results(pkg, setup):
     finally:
         ctx.ad_set_schedule()
         ctx.ad_set_launch_shape(0, 0)
+        ctx.ad_set_work_queue(-1)
+        batch.free()
+
+
+def test_work_queue_with_stopping_runs(pkg, setup):
+    """Runs that stop on their own (autostop; Solis-Wets) with the
+    persistent work queue: items of stopped runs are skipped, packed
+    work-groups whose two halves have both stopped end at once, and every
+    result is bitwise the one without the queue."""
+    ctx, grid, G = setup
+    spec = [(10, 1), (16, 3), (24, 6), (32, 9), (40, 10), (70, 18), (20, 4), (55, 12)]
+    ligs = [synth.ligand(300 + i, n, t) for i, (n, t) in enumerate(spec)]
+    batch = ctx.ad_load_ligands(ligs)
+    cases = [small_params(pkg, nrun=5, max_gens=150, max_evals=10**9, ls_iters=30, autostop=1),
+             small_params(pkg, nrun=4, max_gens=12, ls_method=1, autostop=1)]
+    try:
+        for i, p in enumerate(cases):
+            out = []
+            for mode in (0, 1):
+                ctx.ad_set_work_queue(mode)
+                out.append(ctx.ad_dock_batch(batch, p, 31, per_run=True))
+                assert ctx.ad_get_work_queue() == [mode, mode], (i, mode)
+            if i == 0:
+                assert (out[0]["generations"] < 150).any()   # some runs stopped
+            for k in ("run_energy", "run_genotype", "evals", "best_score", "generations"):
+                assert np.array_equal(out[0][k], out[1][k]), (i, k)
+    finally:
+        ctx.ad_set_work_queue(-1)
         batch.free()
 
 
