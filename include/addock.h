@@ -411,17 +411,39 @@ int ad_get_launch_shape(ad_ctx *ctx, int *unroll, int *wg_per_cu);
 int ad_set_work_queue(ad_ctx *ctx, int mode);
 int ad_get_work_queue(ad_ctx *ctx, int *used);
 
+/* Chains of generation launches (the batching of Sec. 2.2 across
+ * generations).  Every generation launch ends with a tail in which fewer
+ * and fewer work-groups remain, while the next generation of the same runs
+ * has to wait for it.  With parts > 1 each bucket's runs are split into
+ * that many parts (part k: every parts-th packed ligand and every parts-th
+ * one-wavefront run of the longest-first order), and each part's
+ * generation launches go to a stream of its own; the parts meet only at the
+ * end of the docking call (with autostop or Solis-Wets, after every
+ * generation, where the run status is decided), so one part's launch tail
+ * overlaps the other part's launches.  Results are bitwise the same for any
+ * number of parts.  parts 1..4 (default 2); ad_get_chains: parts[2], the
+ * parts per bucket of the last dock call (0: bucket empty).  AD_E_INVALID
+ * for values out of range. */
+int ad_set_chains(ad_ctx *ctx, int parts);
+int ad_get_chains(ad_ctx *ctx, int *parts);
+
 /* ---- diagnostics ----------------------------------------------------------
- * Kernel timing with HIP events recorded on the context's stream around
- * every launch of the docking and scoring kernels, for throughput and
+ * Kernel timing with HIP events recorded around every launch of the docking
+ * and scoring kernels, on the stream the launch goes to, for throughput and
  * roofline reporting.  Kinds: 0 initial population, 1 GA generation,
- * 2 local-search generation (and ad_local_search), 3 scoring.  Times are
- * accumulated when a call completes; ad_get_kernel_timing reads (and with
- * reset != 0 clears) them.  Timing adds two event records per launch. */
+ * 2 local-search generation (and ad_local_search), 3 scoring.  Per kind:
+ * ms, the sum of the launches' durations; launches, their count; busy_ms,
+ * the time during which at least one launch of the kind ran (the union of
+ * their intervals: launches of different chains overlap, ad_set_chains, so
+ * busy_ms <= ms).  Times are accumulated when a call completes;
+ * ad_get_kernel_timing reads (and with reset != 0 clears) them.  Timing
+ * adds two event records per launch and runs the generation loop eagerly
+ * (no graph). */
 #define AD_KERNEL_KINDS 4
 typedef struct {
   double ms[AD_KERNEL_KINDS];
   int64_t launches[AD_KERNEL_KINDS];
+  double busy_ms[AD_KERNEL_KINDS];
 } ad_kernel_times;
 int ad_set_kernel_timing(ad_ctx *ctx, int enable);
 int ad_get_kernel_timing(ad_ctx *ctx, ad_kernel_times *out, int reset);

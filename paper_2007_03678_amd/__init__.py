@@ -33,6 +33,7 @@ EXPORTS = ["ad_create", "ad_destroy", "ad_last_error", "ad_set_stream", "ad_sync
            "ad_score_poses", "ad_score_poses_shape", "ad_score_poses_noalloc", "ad_dock_batch", "ad_dock_select", "ad_local_search", "ad_local_search_shape", "ad_solis_wets", "ad_initial_population",
            "ad_set_kernel_timing", "ad_get_kernel_timing", "ad_set_schedule", "ad_get_schedule", "ad_set_launch_shape",
            "ad_get_launch_shape", "ad_set_work_queue", "ad_get_work_queue",
+           "ad_set_chains", "ad_get_chains",
            "ad_prescreen_n_params", "ad_prescreen_create",
            "ad_prescreen_destroy", "ad_prescreen_set_params", "ad_prescreen_get_params", "ad_prescreen_set_scale",
            "ad_prescreen_get_scale", "ad_prescreen_predict", "ad_prescreen_grad", "ad_prescreen_train"]
@@ -93,7 +94,7 @@ class DockParams(C.Structure):
 
 
 class KernelTimes(C.Structure):
-    _fields_ = [("ms", C.c_double * 4), ("launches", C.c_int64 * 4)]
+    _fields_ = [("ms", C.c_double * 4), ("launches", C.c_int64 * 4), ("busy_ms", C.c_double * 4)]
 
 
 KERNEL_KINDS = ("init", "ga", "ls", "score")
@@ -172,6 +173,8 @@ def lib():
     L.ad_get_launch_shape.argtypes = [vp, ip, ip]
     L.ad_set_work_queue.argtypes = [vp, C.c_int]
     L.ad_get_work_queue.argtypes = [vp, ip]
+    L.ad_set_chains.argtypes = [vp, C.c_int]
+    L.ad_get_chains.argtypes = [vp, ip]
     L.ad_prescreen_n_params.argtypes = []
     L.ad_prescreen_create.argtypes = [vp, C.POINTER(PrescreenCfg), C.c_uint64, C.POINTER(vp)]
     L.ad_prescreen_destroy.argtypes = [vp]
@@ -356,7 +359,9 @@ class Context:
     def ad_get_kernel_timing(self, reset: bool = False):
         t = KernelTimes()
         self._check(lib().ad_get_kernel_timing(self.h, C.byref(t), 1 if reset else 0))
-        return {k: (t.ms[i], int(t.launches[i])) for i, k in enumerate(KERNEL_KINDS)}
+        out = {k: (t.ms[i], int(t.launches[i])) for i, k in enumerate(KERNEL_KINDS)}
+        out["busy_ms"] = {k: t.busy_ms[i] for i, k in enumerate(KERNEL_KINDS)}
+        return out
 
     def ad_set_schedule(self, use_graph=True, autotune=True, stage_pairs=-1, pack_small=True):
         self._check(lib().ad_set_schedule(self.h, int(use_graph), int(autotune), int(stage_pairs), int(pack_small)))
@@ -383,6 +388,15 @@ class Context:
     def ad_get_work_queue(self):
         q = (C.c_int * 2)()
         self._check(lib().ad_get_work_queue(self.h, q))
+        return [q[0], q[1]]
+
+    def ad_set_chains(self, parts=2):
+        """Split every bucket's runs into `parts` chains of launches on their own streams."""
+        self._check(lib().ad_set_chains(self.h, int(parts)))
+
+    def ad_get_chains(self):
+        q = (C.c_int * 2)()
+        self._check(lib().ad_get_chains(self.h, q))
         return [q[0], q[1]]
 
     def ad_synchronize(self):

@@ -236,7 +236,8 @@ extern "C" void ad_destroy(ad_ctx *c) {
     if (c->scratch[s]) hipFree(c->scratch[s]);
   c->free_dock_buffers();
   if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
-  if (c->aux_stream) hipStreamDestroy(c->aux_stream);
+  for (int i = 0; i < ad_ctx::kAuxStreams; ++i)
+    if (c->aux_streams[i]) hipStreamDestroy(c->aux_streams[i]);
   if (c->ev_fork) hipEventDestroy(c->ev_fork);
   if (c->ev_join) hipEventDestroy(c->ev_join);
   delete c;
@@ -890,38 +891,61 @@ void fill_map_build_args(void *out, const ad_forcefield &ff, const ad_grid_desc 
 // ---------------------------------------------------------------------------
 // kernel timing
 // ---------------------------------------------------------------------------
-int ad_ctx::timing_begin(int kind) {
+int ad_ctx::timing_begin(int kind, hipStream_t s) {
   if (!timing) return -1;
-  while (ev_used + 2 > ev_pool.size()) {
+  while (ev_used + 3 > ev_pool.size()) {
     hipEvent_t e;
     if (hipEventCreate(&e) != hipSuccess) return -1;
     ev_pool.push_back(e);
   }
-  const int s = (int)ev_used;
+  // pool slot 0 of a call: the reference event, on the context's stream
+  // before anything the call launches
+  if (ev_used == 0) {
+    if (hipEventRecord(ev_pool[0], stream) != hipSuccess) return -1;
+    ev_used = 1;
+  }
+  const int i = (int)ev_used;
   ev_used += 2;
-  if (hipEventRecord(ev_pool[s], stream) != hipSuccess) return -1;
+  if (hipEventRecord(ev_pool[i], s ? s : stream) != hipSuccess) return -1;
   (void)kind;
-  return s;
+  return i;
 }
 
-void ad_ctx::timing_end(int kind, int start) {
+void ad_ctx::timing_end(int kind, int start, hipStream_t s) {
   if (start < 0) return;
-  if (hipEventRecord(ev_pool[start + 1], stream) != hipSuccess) return;
+  if (hipEventRecord(ev_pool[start + 1], s ? s : stream) != hipSuccess) return;
   ev_pending[kind].push_back({start, start + 1});
 }
 
 void ad_ctx::timing_collect() {
   if (ev_used == 0) return;
-  hipStreamSynchronize(stream);
+  hipStreamSynchronize(stream);   // launches on other streams are joined into it
   for (int k = 0; k < AD_KERNEL_KINDS; ++k) {
+    std::vector<std::pair<float, float>> iv;
     for (auto &pr : ev_pending[k]) {
-      float ms = 0.f;
-      if (hipEventElapsedTime(&ms, ev_pool[pr.first], ev_pool[pr.second]) == hipSuccess) {
-        t_ms[k] += ms;
+      float t0 = 0.f, t1 = 0.f;
+      if (hipEventElapsedTime(&t0, ev_pool[0], ev_pool[pr.first]) == hipSuccess &&
+          hipEventElapsedTime(&t1, ev_pool[0], ev_pool[pr.second]) == hipSuccess) {
+        t_ms[k] += t1 - t0;
         t_launches[k] += 1;
+        iv.push_back({t0, t1});
       }
     }
     ev_pending[k].clear();
+    // busy time: the union of the intervals
+    std::sort(iv.begin(), iv.end());
+    double busy = 0.0, lo = 0.0, hi = -1.0;
+    for (auto &x : iv) {
+      if (x.first > hi) {
+        if (hi > lo) busy += hi - lo;
+        lo = x.first;
+        hi = x.second;
+      } else if (x.second > hi) {
+        hi = x.second;
+      }
+    }
+    if (hi > lo) busy += hi - lo;
+    t_busy[k] += busy;
   }
   ev_used = 0;
 }
@@ -941,9 +965,11 @@ extern "C" int ad_get_kernel_timing(ad_ctx *c, ad_kernel_times *out, int reset) 
   for (int k = 0; k < AD_KERNEL_KINDS; ++k) {
     out->ms[k] = c->t_ms[k];
     out->launches[k] = c->t_launches[k];
+    out->busy_ms[k] = c->t_busy[k];
     if (reset) {
       c->t_ms[k] = 0;
       c->t_launches[k] = 0;
+      c->t_busy[k] = 0;
     }
   }
   return AD_OK;

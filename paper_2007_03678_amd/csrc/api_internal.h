@@ -75,6 +75,8 @@ struct DockArgs {
 
 // ligands packed two individuals per wavefront in the local search
 constexpr int kDualAtoms = 32, kDualTor = 25;
+// chains of generation launches of one docking call, both buckets
+constexpr int kMaxChains = 8;
 
 hipError_t launch_dock_init(const EvalConst &C, int cap, const DockArgs &D, hipStream_t s);
 hipError_t launch_ga_generation(const EvalConst &C, int cap, const DockArgs &D, int gen, hipStream_t s);
@@ -182,6 +184,7 @@ struct ad_ctx {
   std::vector<std::pair<int, int>> ev_pending[AD_KERNEL_KINDS];   // (start, stop) pool indices
   size_t ev_used = 0;
   double t_ms[AD_KERNEL_KINDS] = {0, 0, 0, 0};
+  double t_busy[AD_KERNEL_KINDS] = {0, 0, 0, 0};   // union of the launch intervals
   int64_t t_launches[AD_KERNEL_KINDS] = {0, 0, 0, 0};
   // docking state buffers
   void *dock_buf = nullptr;
@@ -193,7 +196,13 @@ struct ad_ctx {
   bool autotune = true;
   int forced_stage = -1;
   bool pack_small = true;   // two small ligands' individuals per wavefront in the local search
-  hipStream_t aux_stream = nullptr;
+  // chains of generation launches (ad_set_chains): every bucket's runs in
+  // `chains` parts, each on its own stream
+  static constexpr int kMaxChainsPerBucket = 4;
+  static constexpr int kAuxStreams = 2 * kMaxChainsPerBucket - 1;
+  int chains = 2;
+  int last_chains[2] = {0, 0};
+  hipStream_t aux_streams[kAuxStreams] = {};
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   std::map<std::vector<int64_t>, LsChoice> tune_cache;
   int forced_unroll = 0, forced_wgcu = 0;   // 0: tuned
@@ -207,8 +216,10 @@ struct ad_ctx {
 
   int fail(int code, const std::string &msg);
   // timing helpers: mark() before / after a launch of `kind`; collect() after a sync
-  int timing_begin(int kind);
-  void timing_end(int kind, int start);
+  // on stream s (null: the context's stream); the first event of a call is
+  // the reference the intervals are measured from
+  int timing_begin(int kind, hipStream_t s = nullptr);
+  void timing_end(int kind, int start, hipStream_t s = nullptr);
   void timing_collect();
   int hip_fail(hipError_t e, const char *where);
   void *scratch_alloc(size_t bytes, int slot);

@@ -69,12 +69,15 @@ int generations(const ad_dock_params *p, int n_ls) {
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-int ensure_aux(ad_ctx *c) {
-  if (c->aux_stream) return AD_OK;
-  if (hipStreamCreateWithFlags(&c->aux_stream, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess)
-    return c->fail(AD_E_HIP, "cannot create the auxiliary stream");
+// auxiliary streams for `n` chains beyond the first, and the fork / join
+// events
+int ensure_aux(ad_ctx *c, int n) {
+  if (!c->ev_fork && (hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+                      hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess))
+    return c->fail(AD_E_HIP, "cannot create the docking events");
+  for (int i = 0; i < n && i < ad_ctx::kAuxStreams; ++i)
+    if (!c->aux_streams[i] && hipStreamCreateWithFlags(&c->aux_streams[i], hipStreamNonBlocking) != hipSuccess)
+      return c->fail(AD_E_HIP, "cannot create an auxiliary stream");
   return AD_OK;
 }
 
@@ -334,8 +337,9 @@ int dock_impl(ad_ctx *c, const ad_batch *b, int n_lig, const int *sel, const ad_
   const size_t sz_lgen = per_run ? align256((size_t)n_runs * sizeof(int)) : 0;
   const size_t sz_hist = per_run ? align256((size_t)n_runs * 10 * sizeof(float)) : 0;
   const size_t sz_nact = per_run ? align256((size_t)(G + 1) * sizeof(int)) : 0;
-  // work-queue tickets: [bucket][GA, local search][generation 0..G]
-  const size_t sz_q = align256((size_t)4 * (G + 1) * sizeof(unsigned int));
+  // work-queue tickets: [chain][GA, local search][generation 0..G]
+  static_assert(kMaxChains == 2 * ad_ctx::kMaxChainsPerBucket, "two buckets");
+  const size_t sz_q = align256((size_t)2 * kMaxChains * (G + 1) * sizeof(unsigned int));
   const size_t total = sz_geno + sz_E + sz_ev + sz_ord + sz_id + sz_bE + sz_bG + sz_lG + sz_lE + sz_lT + sz_li +
                        sz_map + sz_rl + sz_act + sz_lgen + sz_hist + sz_nact + sz_q;
   hipSetDevice(c->device);
@@ -407,10 +411,12 @@ int dock_impl(ad_ctx *c, const ad_batch *b, int n_lig, const int *sel, const ad_
 
   // runs grouped by kernel atom capacity (bucket 0: <= 64 atoms, bucket 1:
   // <= 128), each bucket in longest-processing-time order so the last
-  // work-groups of every launch are the cheap ones
-  // ADADELTA runs of small ligands (at most kDualAtoms atoms and kDualTor
-  // torsions) go first in bucket 0, as whole ligands: their local search
-  // packs two individuals per wavefront
+  // work-groups of every launch are the cheap ones.  ADADELTA runs of small
+  // ligands (at most kDualAtoms atoms and kDualTor torsions) go first in
+  // bucket 0, as whole ligands: their local search packs two individuals per
+  // wavefront.  A bucket is split into `parts` chains (ad_set_chains): part k
+  // takes every parts-th packed ligand and every parts-th one-wavefront run
+  // of that order, and runs its generations on a stream of its own.
   const bool pack = c->pack_small && p->ls_method == 0 && n_ls > 0 && p->ls_iters > 0;
   std::vector<double> cost(n_lig);
   std::vector<int> bucket_of(n_lig), packed(n_lig);
@@ -420,20 +426,36 @@ int dock_impl(ad_ctx *c, const ad_batch *b, int n_lig, const int *sel, const ad_
     bucket_of[l] = d.n_atoms > 64 ? 1 : 0;
     packed[l] = pack && d.n_atoms <= kDualAtoms && d.n_tor <= kDualTor;
   }
+  struct Chain {
+    int bk, part, start, n, n_dual;
+    DockArgs D;
+  };
+  std::vector<Chain> chains;
   std::vector<int> order;
   order.reserve(n_runs);
-  int bstart[3] = {0, 0, n_runs};
   int n_dual = 0;
   for (int bk = 0; bk < 2; ++bk) {
-    bstart[bk] = (int)order.size();
-    for (int grp = 1; grp >= 0; --grp) {   // bucket 0: the packed group first
-      const size_t g0 = order.size();
-      for (int R = 0; R < n_runs; ++R)
-        if (bucket_of[R / p->nrun] == bk && packed[R / p->nrun] == grp) order.push_back(R);
-      // stable: the runs of one ligand stay consecutive
-      std::stable_sort(order.begin() + g0, order.end(),
-                       [&](int x, int y) { return cost[x / p->nrun] > cost[y / p->nrun]; });
-      if (bk == 0 && grp == 1) n_dual = (int)(order.size() - g0);
+    std::vector<int> ligs;
+    for (int l = 0; l < n_lig; ++l)
+      if (bucket_of[l] == bk) ligs.push_back(l);
+    std::stable_sort(ligs.begin(), ligs.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+    std::vector<int> lig_packed, singles;
+    for (int l : ligs) {
+      if (packed[l]) lig_packed.push_back(l);
+      else
+        for (int r = 0; r < p->nrun; ++r) singles.push_back(l * p->nrun + r);
+    }
+    const int units = (int)(lig_packed.size() + singles.size());
+    const int parts = std::max(1, std::min(c->chains, units));
+    for (int pt = 0; pt < parts; ++pt) {
+      Chain ch{bk, pt, (int)order.size(), 0, 0, D};
+      for (size_t k = pt; k < lig_packed.size(); k += parts)
+        for (int r = 0; r < p->nrun; ++r) order.push_back(lig_packed[k] * p->nrun + r);
+      ch.n_dual = (int)order.size() - ch.start;
+      for (size_t k = pt; k < singles.size(); k += parts) order.push_back(singles[k]);
+      ch.n = (int)order.size() - ch.start;
+      n_dual += ch.n_dual;
+      if (ch.n > 0) chains.push_back(ch);
     }
   }
   std::vector<uint32_t> ids(n_lig);
@@ -449,22 +471,19 @@ int dock_impl(ad_ctx *c, const ad_batch *b, int n_lig, const int *sel, const ad_
   }
 
   const EvalConst C = c->eval_const(b);
-  DockArgs Db[2];
   int max_pairs[2] = {0, 0};
   for (int l = 0; l < n_lig; ++l)
     max_pairs[bucket_of[l]] = std::max(max_pairs[bucket_of[l]], b->lig_host[bidx(l)].n_pairs);
-  int n_buckets = 0;
-  for (int bk = 0; bk < 2; ++bk) {
-    Db[bk] = D;
-    Db[bk].run_order = d_order + bstart[bk];
-    Db[bk].n_launch = bstart[bk + 1] - bstart[bk];
-    Db[bk].stage_pairs = 0;
-    Db[bk].n_dual = bk == 0 ? n_dual : 0;
-    n_buckets += Db[bk].n_launch > 0;
+  const int n_chains = (int)chains.size();
+  for (Chain &ch : chains) {
+    ch.D.run_order = d_order + ch.start;
+    ch.D.n_launch = ch.n;
+    ch.D.stage_pairs = 0;
+    ch.D.n_dual = ch.n_dual;
   }
   {
     const int t0 = c->timing_begin(0);
-    for (int bk = 0; bk < 2; ++bk) HIP_TRY(c, launch_dock_init(C, bk ? 128 : 64, Db[bk], c->stream));
+    for (const Chain &ch : chains) HIP_TRY(c, launch_dock_init(C, ch.bk ? 128 : 64, ch.D, c->stream));
     c->timing_end(0, t0);
   }
   const bool do_ls = n_ls > 0 && p->ls_iters > 0;
@@ -474,57 +493,94 @@ int dock_impl(ad_ctx *c, const ad_batch *b, int n_lig, const int *sel, const ad_
     c->last_unroll[bk] = -1;
     c->last_wgcu[bk] = -1;
     c->last_queue[bk] = -1;
-    if (!Db[bk].n_launch) continue;
+    c->last_chains[bk] = 0;
+    int first = -1;
+    for (int i = 0; i < n_chains; ++i)
+      if (chains[i].bk == bk) {
+        if (first < 0) first = i;
+        ++c->last_chains[bk];
+      }
+    if (first < 0) continue;
     const int cap_b = bk ? 128 : 64;
     // the GA launches take the bucket's queue mode: the local search's
-    // (tuned or forced) under ADADELTA, else the forced one
+    // (tuned or forced) under ADADELTA, else the forced one.  The tuner
+    // times the bucket's first part; every part takes its choice.
     int queue = c->forced_queue > 0 ? 1 : 0;
+    LsChoice ch;
+    bool tuned = false;
     if (do_ls && p->ls_method == 1) {   // Solis-Wets: its own kernel, one fixed shape
       c->last_stage[bk] = 0;
     } else if (do_ls) {
       // packed runs stage no pairs; their launch still takes the tuned shape
-      LsChoice ch;
-      rc = choose_schedule(c, b, sel, n_lig, C, Db[bk], cap_b, max_pairs[bk], Db[bk].n_dual == 0, &ch);
+      bool stage_ok = true;
+      for (const Chain &x : chains)
+        if (x.bk == bk && x.n_dual > 0) stage_ok = false;
+      rc = choose_schedule(c, b, sel, n_lig, C, chains[first].D, cap_b, max_pairs[bk], stage_ok, &ch);
       if (rc) return rc;
-      Db[bk].stage_pairs = ch.stage;
-      Db[bk].ls_unroll = ch.unroll;
-      Db[bk].ls_pad = pad_for(ls_workgroup_lds(C, cap_b, Db[bk]), ch.wg_per_cu);
+      tuned = true;
       c->last_stage[bk] = ch.stage;
       c->last_unroll[bk] = ch.unroll;
       c->last_wgcu[bk] = ch.wg_per_cu;
       queue = ch.queue;
-      if (queue) {
-        Db[bk].q_ls = d_q + (size_t)(2 * bk + 1) * (G + 1);
-        Db[bk].q_grid_ls = queue_grid(C, cap_b, Db[bk], 1);
-        if (Db[bk].q_grid_ls <= 0) return c->fail(AD_E_HIP, "cannot size the work-queue grid");
-      }
     }
-    if (queue) {
-      Db[bk].q_ga = d_q + (size_t)(2 * bk) * (G + 1);
-      Db[bk].q_grid_ga = queue_grid(C, cap_b, Db[bk], 0);
-      if (Db[bk].q_grid_ga <= 0) return c->fail(AD_E_HIP, "cannot size the work-queue grid");
+    for (int i = 0; i < n_chains; ++i) {
+      if (chains[i].bk != bk) continue;
+      DockArgs &Dc = chains[i].D;
+      if (tuned) {
+        Dc.stage_pairs = ch.stage;
+        Dc.ls_unroll = ch.unroll;
+        Dc.ls_pad = pad_for(ls_workgroup_lds(C, cap_b, Dc), ch.wg_per_cu);
+      }
+      if (queue) {
+        Dc.q_ga = d_q + (size_t)(2 * i) * (G + 1);
+        Dc.q_grid_ga = queue_grid(C, cap_b, Dc, 0);
+        if (tuned) {
+          Dc.q_ls = d_q + (size_t)(2 * i + 1) * (G + 1);
+          Dc.q_grid_ls = queue_grid(C, cap_b, Dc, 1);
+        }
+        if (Dc.q_grid_ga <= 0 || (tuned && Dc.q_grid_ls <= 0))
+          return c->fail(AD_E_HIP, "cannot size the work-queue grid");
+      }
     }
     c->last_queue[bk] = queue;
   }
 
-  // the generation loop: bucket 0 on the context's stream, bucket 1 on the
-  // auxiliary stream.  Eager with kernel timing (phases forked and joined
-  // so each phase is timed on the context's stream); otherwise captured once
-  // into a graph whose two bucket chains run independently, and replayed.
-  if (n_buckets == 2) {
-    rc = ensure_aux(c);
-    if (rc) return rc;
-  }
-  hipStream_t bs[2] = {c->stream, n_buckets == 2 ? c->aux_stream : c->stream};
+  // the generation loop: chain 0 on the context's stream, the others on
+  // auxiliary streams; the chains meet only at the end (with per-run
+  // stopping, after every generation, for the status kernel).  Eager with
+  // kernel timing (an event pair around every launch, on its stream),
+  // otherwise captured once into a graph and replayed.
+  rc = ensure_aux(c, n_chains - 1);
+  if (rc) return rc;
+  std::vector<hipStream_t> cs(n_chains);
+  for (int i = 0; i < n_chains; ++i) cs[i] = i == 0 ? c->stream : c->aux_streams[i - 1];
   auto fork = [&]() -> hipError_t {
-    if (n_buckets < 2) return hipSuccess;
+    if (n_chains < 2) return hipSuccess;
     hipError_t e = hipEventRecord(c->ev_fork, c->stream);
-    return e != hipSuccess ? e : hipStreamWaitEvent(c->aux_stream, c->ev_fork, 0);
+    for (int i = 1; i < n_chains && e == hipSuccess; ++i) e = hipStreamWaitEvent(cs[i], c->ev_fork, 0);
+    return e;
   };
   auto join = [&]() -> hipError_t {
-    if (n_buckets < 2) return hipSuccess;
-    hipError_t e = hipEventRecord(c->ev_join, c->aux_stream);
-    return e != hipSuccess ? e : hipStreamWaitEvent(c->stream, c->ev_join, 0);
+    hipError_t e = hipSuccess;
+    for (int i = 1; i < n_chains && e == hipSuccess; ++i) {
+      e = hipEventRecord(c->ev_join, cs[i]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(c->stream, c->ev_join, 0);
+    }
+    return e;
+  };
+  // one generation of chain i (GA, then local search), each launch timed
+  auto generation = [&](int i, int gen) -> hipError_t {
+    const Chain &ch = chains[i];
+    const int cap_i = ch.bk ? 128 : 64;
+    const int t1 = c->timing_begin(1, cs[i]);
+    hipError_t e = launch_ga_generation(C, cap_i, ch.D, gen, cs[i]);
+    c->timing_end(1, t1, cs[i]);
+    if (e == hipSuccess && do_ls) {
+      const int t2 = c->timing_begin(2, cs[i]);
+      e = launch_ls_generation(C, cap_i, ch.D, gen, cs[i]);
+      c->timing_end(2, t2, cs[i]);
+    }
+    return e;
   };
   const bool graph = c->use_graph && !c->timing && G > 0 && !per_run;
   c->last_graph = graph ? 1 : 0;
@@ -534,18 +590,9 @@ int dock_impl(ad_ctx *c, const ad_batch *b, int n_lig, const int *sel, const ad_
     // per run after each generation; the host looks every 16 generations
     HIP_TRY(c, launch_run_status(D, 0, c->stream));
     for (int gen = 1; gen <= G; ++gen) {
-      const int t1 = c->timing_begin(1);
       HIP_TRY(c, fork());
-      for (int bk = 0; bk < 2; ++bk) HIP_TRY(c, launch_ga_generation(C, bk ? 128 : 64, Db[bk], gen, bs[bk]));
+      for (int i = 0; i < n_chains; ++i) HIP_TRY(c, generation(i, gen));
       HIP_TRY(c, join());
-      c->timing_end(1, t1);
-      if (do_ls) {
-        const int t2 = c->timing_begin(2);
-        HIP_TRY(c, fork());
-        for (int bk = 0; bk < 2; ++bk) HIP_TRY(c, launch_ls_generation(C, bk ? 128 : 64, Db[bk], gen, bs[bk]));
-        HIP_TRY(c, join());
-        c->timing_end(2, t2);
-      }
       HIP_TRY(c, launch_run_status(D, gen, c->stream));
       if (gen % 16 == 0 || gen == G) {
         int n_act = 0;
@@ -555,30 +602,18 @@ int dock_impl(ad_ctx *c, const ad_batch *b, int n_lig, const int *sel, const ad_
       }
     }
   } else if (!graph) {
-    for (int gen = 1; gen <= G; ++gen) {
-      const int t1 = c->timing_begin(1);
-      HIP_TRY(c, fork());
-      for (int bk = 0; bk < 2; ++bk) HIP_TRY(c, launch_ga_generation(C, bk ? 128 : 64, Db[bk], gen, bs[bk]));
-      HIP_TRY(c, join());
-      c->timing_end(1, t1);
-      if (do_ls) {
-        const int t2 = c->timing_begin(2);
-        HIP_TRY(c, fork());
-        for (int bk = 0; bk < 2; ++bk) HIP_TRY(c, launch_ls_generation(C, bk ? 128 : 64, Db[bk], gen, bs[bk]));
-        HIP_TRY(c, join());
-        c->timing_end(2, t2);
-      }
-    }
+    // generation-major, so every stream is fed as the loop goes
+    HIP_TRY(c, fork());
+    for (int gen = 1; gen <= G; ++gen)
+      for (int i = 0; i < n_chains; ++i) HIP_TRY(c, generation(i, gen));
+    HIP_TRY(c, join());
   } else {
     hipGraph_t g = nullptr;
     hipGraphExec_t ge = nullptr;
     HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
     hipError_t e = fork();
     for (int gen = 1; gen <= G && e == hipSuccess; ++gen)
-      for (int bk = 0; bk < 2 && e == hipSuccess; ++bk) {
-        e = launch_ga_generation(C, bk ? 128 : 64, Db[bk], gen, bs[bk]);
-        if (e == hipSuccess && do_ls) e = launch_ls_generation(C, bk ? 128 : 64, Db[bk], gen, bs[bk]);
-      }
+      for (int i = 0; i < n_chains && e == hipSuccess; ++i) e = generation(i, gen);
     if (e == hipSuccess) e = join();
     const hipError_t e_end = hipStreamEndCapture(c->stream, &g);
     if (e != hipSuccess || e_end != hipSuccess) {
@@ -771,6 +806,20 @@ extern "C" int ad_get_work_queue(ad_ctx *c, int *used) {
   if (!c) return AD_E_INVALID;
   if (used)
     for (int bk = 0; bk < 2; ++bk) used[bk] = c->last_queue[bk];
+  return AD_OK;
+}
+
+extern "C" int ad_set_chains(ad_ctx *c, int parts) {
+  if (!c) return AD_E_INVALID;
+  if (parts < 1 || parts > ad_ctx::kMaxChainsPerBucket) return c->fail(AD_E_INVALID, "chains: parts 1..4 per bucket");
+  c->chains = parts;
+  return AD_OK;
+}
+
+extern "C" int ad_get_chains(ad_ctx *c, int *parts) {
+  if (!c) return AD_E_INVALID;
+  if (parts)
+    for (int bk = 0; bk < 2; ++bk) parts[bk] = c->last_chains[bk];
   return AD_OK;
 }
 

@@ -33,7 +33,7 @@ def test_traffic_is_reported_only_for_the_profiled_source(tmp_path):
     src.write_text("// kernel source\n")
     h = hashlib.sha256(src.read_bytes()).hexdigest()
     prof = tmp_path / "profile.md"
-    prof.write_text(f"# summary\n\ntraffic_kernel_sha256: {h}\ntraffic_bytes_per_launch: 1449129700\n")
+    prof.write_text(f"# summary\n\ntraffic_kernel_sha256: {h}\ntraffic_bytes_per_generation: 1449129700\n")
     assert b.measured_traffic(str(prof), str(src)) == 1449129700.0
     src.write_text("// kernel source, changed\n")
     assert b.measured_traffic(str(prof), str(src)) is None

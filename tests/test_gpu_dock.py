@@ -225,6 +225,20 @@ def test_schedules_give_identical_results(pkg, setup):
         assert ctx.ad_get_work_queue() == [0, 0]
         assert np.array_equal(r["run_energy"], ref["run_energy"])
         ctx.ad_set_work_queue(-1)
+        # chains of launches: each bucket's runs in parts on their own
+        # streams, with and without the queue, graph and eager with timing
+        for parts, queue, timing in [(1, 0, False), (3, 1, False), (4, 0, False), (2, 0, True), (3, 0, True)]:
+            ctx.ad_set_chains(parts)
+            ctx.ad_set_work_queue(queue)
+            ctx.ad_set_kernel_timing(timing)
+            r = ctx.ad_dock_batch(batch, p, 77, per_run=True)
+            ctx.ad_set_kernel_timing(False)
+            assert ctx.ad_get_chains()[0] == parts and 1 <= ctx.ad_get_chains()[1] <= parts
+            assert ctx.ad_get_schedule()["graph"] == (not timing)
+            for k in ("run_energy", "run_genotype", "evals", "best_score"):
+                assert np.array_equal(r[k], ref[k]), ("chains", parts, queue, timing, k)
+        ctx.ad_set_chains(2)
+        ctx.ad_set_work_queue(-1)
         # kernel timing runs the loop eagerly, with the same results
         ctx.ad_set_kernel_timing(True)
         r = ctx.ad_dock_batch(batch, p, 77, per_run=True)
@@ -239,6 +253,7 @@ def test_schedules_give_identical_results(pkg, setup):
         ctx.ad_set_schedule()
         ctx.ad_set_launch_shape(0, 0)
         ctx.ad_set_work_queue(-1)
+        ctx.ad_set_chains(2)
         batch.free()
 
 
@@ -256,16 +271,19 @@ def test_work_queue_with_stopping_runs(pkg, setup):
     try:
         for i, p in enumerate(cases):
             out = []
-            for mode in (0, 1):
+            for mode, parts in ((0, 1), (1, 1), (1, 2), (0, 3)):
                 ctx.ad_set_work_queue(mode)
+                ctx.ad_set_chains(parts)
                 out.append(ctx.ad_dock_batch(batch, p, 31, per_run=True))
                 assert ctx.ad_get_work_queue() == [mode, mode], (i, mode)
             if i == 0:
                 assert (out[0]["generations"] < 150).any()   # some runs stopped
-            for k in ("run_energy", "run_genotype", "evals", "best_score", "generations"):
-                assert np.array_equal(out[0][k], out[1][k]), (i, k)
+            for o in out[1:]:
+                for k in ("run_energy", "run_genotype", "evals", "best_score", "generations"):
+                    assert np.array_equal(out[0][k], o[k]), (i, k)
     finally:
         ctx.ad_set_work_queue(-1)
+        ctx.ad_set_chains(2)
         batch.free()
 
 
