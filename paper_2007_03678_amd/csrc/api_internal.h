@@ -77,6 +77,15 @@ struct DockArgs {
 constexpr int kDualAtoms = 32, kDualTor = 25;
 // chains of generation launches of one docking call, both buckets
 constexpr int kMaxChains = 8;
+// The ADADELTA local search keeps its pick permutation (pop - 1 ints) in
+// the torsion-transform area of the evaluation LDS, which is free until the
+// search starts, when it fits (and the launch has no staged pairs);
+// otherwise in dynamic LDS.  Capacity: the packed layout's area,
+// kDualTor x 12 doubles.
+constexpr int kPermAlias = kDualTor * 12 * 2;
+__host__ __device__ inline bool perm_aliased(int pop, int stage_pairs) {
+  return stage_pairs <= 0 && pop - 1 <= kPermAlias;
+}
 
 hipError_t launch_dock_init(const EvalConst &C, int cap, const DockArgs &D, hipStream_t s);
 hipError_t launch_ga_generation(const EvalConst &C, int cap, const DockArgs &D, int gen, hipStream_t s);

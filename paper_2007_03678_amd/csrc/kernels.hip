@@ -1063,7 +1063,9 @@ __device__ __forceinline__ void ls_dual(const EvalConst &C, const DockArgs &D, i
   const int half = threadIdx.x >> 5, lane = threadIdx.x & 31;
   EvalLds<kDualAtoms, kDualTor> &S = S2[half];
   init_eval_lds(S, lane);
-  int *perm = reinterpret_cast<int *>(dyn_lds) + half * D.pop;
+  static_assert(sizeof(S.tm) >= kPermAlias * sizeof(int), "pick permutation alias");
+  int *perm = perm_aliased(D.pop, 0) ? reinterpret_cast<int *>(&S.tm[0][0])
+                                     : reinterpret_cast<int *>(dyn_lds) + half * D.pop;
   const int items = D.nrun * D.n_ls;
   const int wpl = (items + 1) >> 1;   // work-groups per ligand
   const int chunk = wg / wpl;
@@ -1110,7 +1112,9 @@ __device__ __forceinline__ void ls_dual(const EvalConst &C, const DockArgs &D, i
 template <int CAP, bool STAGE, int UNROLL>
 __device__ __forceinline__ void ls_single(const EvalConst &C, const DockArgs &D, int gen, int item, EvalLds<CAP> &S) {
   extern __shared__ __attribute__((aligned(16))) char dyn_lds[];
-  int *perm = reinterpret_cast<int *>(dyn_lds);
+  static_assert(sizeof(S.tm) >= kPermAlias * sizeof(int), "pick permutation alias");
+  int *perm = !STAGE && perm_aliased(D.pop, 0) ? reinterpret_cast<int *>(&S.tm[0][0])
+                                               : reinterpret_cast<int *>(dyn_lds);
   const int lane = threadIdx.x;
   const int R = D.run_order[D.n_dual + item / D.n_ls];
   if (D.active && !D.active[R]) return;
@@ -1620,7 +1624,7 @@ hipError_t launch_ga_generation(const EvalConst &C, int cap, const DockArgs &D, 
 }
 
 size_t ls_dynamic_lds(const EvalConst &C, const DockArgs &D) {
-  if (D.stage_pairs <= 0) return (size_t)D.pop * sizeof(int);
+  if (D.stage_pairs <= 0) return perm_aliased(D.pop, 0) ? 0 : (size_t)D.pop * sizeof(int);
   return (size_t)stage_offset(D.pop) + (size_t)C.ff.n_types * C.ff.n_types * 16 + (size_t)D.stage_pairs * 16;
 }
 
@@ -1629,7 +1633,7 @@ size_t ls_workgroup_lds(const EvalConst &C, int cap, const DockArgs &D) {
     const size_t one = sizeof(EvalLds<64>), two = 2 * sizeof(EvalLds<kDualAtoms, kDualTor>);
     const bool packed = D.ls_method == 0 && D.n_dual > 0 && D.stage_pairs <= 0;
     return (D.stage_pairs > 0 ? one : std::max(one, two)) +
-           (packed ? 2 * (size_t)D.pop * sizeof(int) : ls_dynamic_lds(C, D));
+           (packed ? (perm_aliased(D.pop, 0) ? 0 : 2 * (size_t)D.pop * sizeof(int)) : ls_dynamic_lds(C, D));
   }
   return sizeof(EvalLds<128>) + ls_dynamic_lds(C, D);
 }
@@ -1675,7 +1679,7 @@ LsLaunch ls_launch_of(const EvalConst &C, int cap, const DockArgs &D) {
   L.packed = cap <= 64 && D.n_dual > 0 && D.stage_pairs <= 0;
   L.stage = D.stage_pairs > 0;
   if (L.packed) {
-    L.dyn = 2 * (size_t)D.pop * sizeof(int) + pad;
+    L.dyn = (perm_aliased(D.pop, 0) ? 0 : 2 * (size_t)D.pop * sizeof(int)) + pad;
     L.n_items = (long long)(D.n_launch - D.n_dual) * D.n_ls + (long long)(D.n_dual / D.nrun) * ((D.nrun * D.n_ls + 1) / 2);
   } else {
     DockArgs t = D;
@@ -1737,7 +1741,7 @@ hipError_t launch_ls_generation(const EvalConst &C, int cap, const DockArgs &D0,
     const long long wpl = (D0.nrun * D0.n_ls + 1) / 2;
     const long long n_chunks = D0.n_dual / D0.nrun;
     const long long n_single = (long long)(D0.n_launch - D0.n_dual) * D0.n_ls;
-    const size_t dyn = 2 * (size_t)D0.pop * sizeof(int) + pad;
+    const size_t dyn = (perm_aliased(D0.pop, 0) ? 0 : 2 * (size_t)D0.pop * sizeof(int)) + pad;
     if (n_single + n_chunks * wpl <= max_blocks) {
       launch_ls_kernel<64, false>(ur, dim3((unsigned)(n_single + n_chunks * wpl)), dyn, s, C, D0, gen);
       return hipGetLastError();
