@@ -418,12 +418,13 @@ int ad_get_work_queue(ad_ctx *ctx, int *used);
  * that many parts (part k: every parts-th packed ligand and every parts-th
  * one-wavefront run of the longest-first order), and each part's
  * generation launches go to a stream of its own; the parts meet only at the
- * end of the docking call (with autostop or Solis-Wets, after every
- * generation, where the run status is decided), so one part's launch tail
- * overlaps the other part's launches.  Results are bitwise the same for any
- * number of parts.  parts 1..4 (default 2); ad_get_chains: parts[2], the
- * parts per bucket of the last dock call (0: bucket empty).  AD_E_INVALID
- * for values out of range. */
+ * end of the docking call, so one part's launch tail overlaps the other
+ * part's launches.  Calls whose runs stop on their own (autostop,
+ * Solis-Wets) decide every run's status after every generation, where the
+ * parts would have to meet: they keep one part per bucket.  Results are
+ * bitwise the same for any number of parts.  parts 1..4 (default 2);
+ * ad_get_chains: parts[2], the parts per bucket of the last dock call (0:
+ * bucket empty).  AD_E_INVALID for values out of range. */
 int ad_set_chains(ad_ctx *ctx, int parts);
 int ad_get_chains(ad_ctx *ctx, int *parts);
 

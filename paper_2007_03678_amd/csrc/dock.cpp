@@ -445,8 +445,10 @@ int dock_impl(ad_ctx *c, const ad_batch *b, int n_lig, const int *sel, const ad_
       else
         for (int r = 0; r < p->nrun; ++r) singles.push_back(l * p->nrun + r);
     }
+    // runs that stop on their own meet after every generation (status
+    // kernel), where split launches would only add tails: one part
     const int units = (int)(lig_packed.size() + singles.size());
-    const int parts = std::max(1, std::min(c->chains, units));
+    const int parts = per_run ? 1 : std::max(1, std::min(c->chains, units));
     for (int pt = 0; pt < parts; ++pt) {
       Chain ch{bk, pt, (int)order.size(), 0, 0, D};
       for (size_t k = pt; k < lig_packed.size(); k += parts)

@@ -262,7 +262,8 @@ def test_work_queue_with_stopping_runs(pkg, setup):
     """Runs that stop on their own (autostop; Solis-Wets) with the
     persistent work queue: items of stopped runs are skipped, packed
     work-groups whose two halves have both stopped end at once, and every
-    result is bitwise the one without the queue."""
+    result is bitwise the one without the queue.  Such calls keep one chain
+    of launches per bucket whatever ad_set_chains asks."""
     ctx, grid, G = setup
     spec = [(10, 1), (16, 3), (24, 6), (32, 9), (40, 10), (70, 18), (20, 4), (55, 12)]
     ligs = [synth.ligand(300 + i, n, t) for i, (n, t) in enumerate(spec)]
@@ -277,6 +278,7 @@ def test_work_queue_with_stopping_runs(pkg, setup):
                 ctx.ad_set_chains(parts)
                 out.append(ctx.ad_dock_batch(batch, p, 31, per_run=True))
                 assert ctx.ad_get_work_queue() == [mode, mode], (i, mode)
+                assert ctx.ad_get_chains() == [1, 1]   # stopping runs: one part per bucket
             if i == 0:
                 assert (out[0]["generations"] < 150).any()   # some runs stopped
             for o in out[1:]:
