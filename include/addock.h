@@ -30,6 +30,7 @@
 #ifndef ADDOCK_H
 #define ADDOCK_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -448,6 +449,23 @@ typedef struct {
 } ad_kernel_times;
 int ad_set_kernel_timing(ad_ctx *ctx, int enable);
 int ad_get_kernel_timing(ad_ctx *ctx, ad_kernel_times *out, int reset);
+
+/* Microbenchmarks of the rates the kernels' rooflines are set against (the
+ * measurement of the method's cost, Sec. 3; diagnostics, never called by the
+ * docking path).  kind:
+ *   0  FP32 vector FMA, non-packed (as the library is built): FLOP/s
+ *   1  FP64 vector FMA: FLOP/s
+ *   2  FP32 exp2 (the transcendental unit): results/s
+ *   3  LDS ds_add_f64 on consecutive addresses, one-wavefront work-groups:
+ *      lane additions/s
+ *   4  random 16-byte gathers from a device buffer of `bytes` bytes
+ *      (4 KiB .. 16 GiB, used up to the largest power-of-two record count
+ *      that fits; L2-sized or map-sized): bytes/s
+ * Each runs about 16 work-groups per CU on the context's stream, best of
+ * three timed launches after a warm-up; the call allocates and frees its
+ * own device buffers and synchronises.  *result receives the rate.
+ * AD_E_INVALID for a bad kind or size, AD_E_OOM, AD_E_HIP. */
+int ad_microbench(ad_ctx *ctx, int kind, size_t bytes, double *result);
 
 
 /* ---- learned pre-screen ---------------------------------------------------

@@ -19,7 +19,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB_PATH = os.path.join(HERE, "libaddock.so")
-SOURCES = ["csrc/prep.cpp", "csrc/api.cpp", "csrc/dock.cpp", "csrc/kernels.hip", "csrc/prescreen.hip"]
+SOURCES = ["csrc/prep.cpp", "csrc/api.cpp", "csrc/dock.cpp", "csrc/kernels.hip", "csrc/prescreen.hip",
+           "csrc/microbench.hip"]
 
 AD_OK, AD_E_INVALID, AD_E_NOMAP, AD_E_OOM, AD_E_DEVICE, AD_E_STATE, AD_E_UNSUPPORTED, AD_E_HIP = 0, -1, -2, -3, -4, -5, -6, -7
 ERR_NAMES = {0: "AD_OK", -1: "AD_E_INVALID", -2: "AD_E_NOMAP", -3: "AD_E_OOM", -4: "AD_E_DEVICE",
@@ -33,7 +34,7 @@ EXPORTS = ["ad_create", "ad_destroy", "ad_last_error", "ad_set_stream", "ad_sync
            "ad_score_poses", "ad_score_poses_shape", "ad_score_poses_noalloc", "ad_dock_batch", "ad_dock_select", "ad_local_search", "ad_local_search_shape", "ad_solis_wets", "ad_initial_population",
            "ad_set_kernel_timing", "ad_get_kernel_timing", "ad_set_schedule", "ad_get_schedule", "ad_set_launch_shape",
            "ad_get_launch_shape", "ad_set_work_queue", "ad_get_work_queue",
-           "ad_set_chains", "ad_get_chains",
+           "ad_set_chains", "ad_get_chains", "ad_microbench",
            "ad_prescreen_n_params", "ad_prescreen_create",
            "ad_prescreen_destroy", "ad_prescreen_set_params", "ad_prescreen_get_params", "ad_prescreen_set_scale",
            "ad_prescreen_get_scale", "ad_prescreen_predict", "ad_prescreen_grad", "ad_prescreen_train"]
@@ -174,6 +175,7 @@ def lib():
     L.ad_set_work_queue.argtypes = [vp, C.c_int]
     L.ad_get_work_queue.argtypes = [vp, ip]
     L.ad_set_chains.argtypes = [vp, C.c_int]
+    L.ad_microbench.argtypes = [vp, C.c_int, C.c_size_t, C.POINTER(C.c_double)]
     L.ad_get_chains.argtypes = [vp, ip]
     L.ad_prescreen_n_params.argtypes = []
     L.ad_prescreen_create.argtypes = [vp, C.POINTER(PrescreenCfg), C.c_uint64, C.POINTER(vp)]
@@ -393,6 +395,15 @@ class Context:
     def ad_set_chains(self, parts=2):
         """Split every bucket's runs into `parts` chains of launches on their own streams."""
         self._check(lib().ad_set_chains(self.h, int(parts)))
+
+    MICROBENCH_KINDS = ("fma_f32_flops", "fma_f64_flops", "exp2_f32_per_s", "lds_add_f64_per_s", "gather_bytes_per_s")
+
+    def ad_microbench(self, kind, nbytes=0):
+        """Rate measured by microbenchmark `kind` (index or name of MICROBENCH_KINDS); nbytes: gather buffer."""
+        k = self.MICROBENCH_KINDS.index(kind) if isinstance(kind, str) else int(kind)
+        out = C.c_double()
+        self._check(lib().ad_microbench(self.h, k, int(nbytes), C.byref(out)))
+        return out.value
 
     def ad_get_chains(self):
         q = (C.c_int * 2)()
