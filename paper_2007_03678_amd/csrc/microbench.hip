@@ -115,15 +115,15 @@ extern "C" int ad_microbench(ad_ctx *c, int kind, size_t bytes, double *result) 
       hipFree(out);
       return c->fail(AD_E_OOM, "microbenchmark gather buffer");
     }
-    hipMemsetAsync(buf, 0, (size_t)n_rec * 16, c->stream);
   }
-  hipEvent_t e0, e1;
-  hipEventCreate(&e0);
-  hipEventCreate(&e1);
+  hipError_t err = buf ? hipMemsetAsync(buf, 0, (size_t)n_rec * 16, c->stream) : hipSuccess;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (err == hipSuccess) err = hipEventCreate(&e0);
+  if (err == hipSuccess) err = hipEventCreate(&e1);
   float best = INFINITY;
-  hipError_t err = hipSuccess;
   for (int rep = 0; rep < 4 && err == hipSuccess; ++rep) {   // the first is a warm-up
-    hipEventRecord(e0, c->stream);
+    err = hipEventRecord(e0, c->stream);
+    if (err != hipSuccess) break;
     switch (kind) {
       case 0: hipLaunchKernelGGL(k_mb_fma<float>, dim3(blocks), dim3(kMbBlock), 0, c->stream, (float *)out, 0.5f); break;
       case 1: hipLaunchKernelGGL(k_mb_fma<double>, dim3(blocks), dim3(kMbBlock), 0, c->stream, (double *)out, 0.5); break;
@@ -134,14 +134,14 @@ extern "C" int ad_microbench(ad_ctx *c, int kind, size_t bytes, double *result) 
                            (float *)out);
     }
     err = hipGetLastError();
-    hipEventRecord(e1, c->stream);
+    if (err == hipSuccess) err = hipEventRecord(e1, c->stream);
     if (err == hipSuccess) err = hipEventSynchronize(e1);
     float ms = 0.0f;
     if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
     if (rep > 0) best = std::min(best, ms);
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  if (e0) hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
   hipFree(out);
   if (buf) hipFree(buf);
   if (err != hipSuccess) return c->hip_fail(err, "microbenchmark");
