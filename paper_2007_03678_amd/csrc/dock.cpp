@@ -427,7 +427,7 @@ int dock_impl(ad_ctx *c, const ad_batch *b, int n_lig, const int *sel, const ad_
     packed[l] = pack && d.n_atoms <= kDualAtoms && d.n_tor <= kDualTor;
   }
   struct Chain {
-    int bk, part, start, n, n_dual;
+    int bk, start, n, n_dual;
     DockArgs D;
   };
   std::vector<Chain> chains;
@@ -450,7 +450,7 @@ int dock_impl(ad_ctx *c, const ad_batch *b, int n_lig, const int *sel, const ad_
     const int units = (int)(lig_packed.size() + singles.size());
     const int parts = per_run ? 1 : std::max(1, std::min(c->chains, units));
     for (int pt = 0; pt < parts; ++pt) {
-      Chain ch{bk, pt, (int)order.size(), 0, 0, D};
+      Chain ch{bk, (int)order.size(), 0, 0, D};
       for (size_t k = pt; k < lig_packed.size(); k += parts)
         for (int r = 0; r < p->nrun; ++r) order.push_back(lig_packed[k] * p->nrun + r);
       ch.n_dual = (int)order.size() - ch.start;
