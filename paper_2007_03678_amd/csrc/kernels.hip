@@ -372,7 +372,7 @@ __device__ __forceinline__ double grid_energy(const GridArgs &G, double k_out, i
 __device__ __forceinline__ float pair_energy(const FFConst &K, const LJRec &lj, float qq, float dsv, float r2,
                                              float *fscale) {
   const bool floored = !(r2 >= K.r_floor2);
-  const float r2c = fmaxf(r2, K.r_floor2);   // NaN -> the floor, as the comparison above
+  const float r2c = floored ? K.r_floor2 : r2;   // NaN -> the floor
   const float inv_r = fast_rsq(r2c);
   const float r = r2c * inv_r;
   // smoothed 12-6 / 12-10
@@ -520,36 +520,89 @@ __device__ double evaluate(const EvalConst &C, const LaneLig<CAP> &LL, EvalLds<C
     rec_b = (STAGE && lane + W < st.n) ? s_pr[lane + W] : pr[lane + W];
     lj_a = STAGE ? s_lj[rec_a.ijt >> 16] : ljt[rec_a.ijt >> 16];
   }
+  // 32-bit byte offsets from the ligand's list (a list and its spare records
+  // span far less than 4 GiB)
+  auto pair_at = [&](int q) -> PairRec {
+    return (STAGE && q < st.n) ? s_pr[q]
+                               : *reinterpret_cast<const PairRec *>(reinterpret_cast<const char *>(pr) +
+                                                                    (uint32_t)q * (uint32_t)sizeof(PairRec));
+  };
+  auto lj_of = [&](const PairRec &r) -> LJRec { return STAGE ? s_lj[r.ijt >> 16] : ljt[r.ijt >> 16]; };
+  // One pair step.  A lane with `live` false (past the list, in the second
+  // step of a trip) computes on a record that is not the ligand's and keeps
+  // its sum and the forces unchanged; its atom indices are cut to the array
+  // (the ligand's own indices are below CAP, a power of two).
+  static_assert((CAP & (CAP - 1)) == 0, "atom index mask");
+  struct PairGeo {
+    int i, j;
+    double dx, dy, dz;
+  };
+  auto pair_geo = [&](const PairRec &rec) -> PairGeo {
+    const int i = rec.ijt & (CAP - 1), j = (rec.ijt >> 8) & (CAP - 1);
+    return PairGeo{i, j, S.x[0][i] - S.x[0][j], S.x[1][i] - S.x[1][j], S.x[2][i] - S.x[2][j]};
+  };
+  auto pair_terms = [&](const PairRec &rec, const LJRec &lj, const PairGeo &g, bool live) {
+    const float r2 = (float)(g.dx * g.dx + g.dy * g.dy + g.dz * g.dz);
+    float fs;
+    const double e = (double)pair_energy(C.ff, lj, rec.qq, rec.dsv, r2, &fs);
+    e_intra = live ? e_intra + e : e_intra;   // a select: the terms stay out of the branch below
+    if (GRAD && live) {
+      const double f = (double)fs;
+      const double fx = f * g.dx, fy = f * g.dy, fz = f * g.dz;
+      atomicAdd(&S.g[g.i][0], fx);
+      atomicAdd(&S.g[g.i][1], fy);
+      atomicAdd(&S.g[g.i][2], fz);
+      atomicAdd(&S.g[g.j][0], -fx);
+      atomicAdd(&S.g[g.j][1], -fy);
+      atomicAdd(&S.g[g.j][2], -fz);
+    }
+  };
+  auto do_pair = [&](const PairRec &rec, const LJRec &lj, bool live) { pair_terms(rec, lj, pair_geo(rec), live); };
   // The step count is the same for every lane of the group (the last step
   // masks the lanes past the list), so step k of every lane is one and the
-  // same instruction whatever the unroll: UNROLL (a launch-shape option of
-  // the local search) then changes neither a lane's order of pairs nor the
-  // order in which the lanes' force additions reach an accumulator.
+  // same instruction in either loop form below: the form (a launch-shape
+  // option of the local search) then changes neither a lane's order of pairs
+  // nor the order in which the lanes' force additions reach an accumulator.
   const int n_steps = (L.n_pairs + W - 1) / W;
-#pragma unroll UNROLL
-  for (int step = 0; step < n_steps; ++step) {
-    const int p = step * W + lane;
-    if (p >= L.n_pairs) continue;
-    const PairRec rec = rec_a;
-    const LJRec lj = lj_a;
-    rec_a = rec_b;
-    rec_b = (STAGE && p + 2 * W < st.n) ? s_pr[p + 2 * W] : pr[p + 2 * W];
-    lj_a = STAGE ? s_lj[rec_a.ijt >> 16] : ljt[rec_a.ijt >> 16];
-    const int i = rec.ijt & 0xff, j = (rec.ijt >> 8) & 0xff;
-    const double dx = S.x[0][i] - S.x[0][j], dy = S.x[1][i] - S.x[1][j], dz = S.x[2][i] - S.x[2][j];
-    const float r2 = (float)(dx * dx + dy * dy + dz * dz);
-    float fs;
-    e_intra += (double)pair_energy(C.ff, lj, rec.qq, rec.dsv, r2, &fs);
-    if (GRAD) {
-      const double f = (double)fs;
-      const double fx = f * dx, fy = f * dy, fz = f * dz;
-      atomicAdd(&S.g[i][0], fx);
-      atomicAdd(&S.g[i][1], fy);
-      atomicAdd(&S.g[i][2], fz);
-      atomicAdd(&S.g[j][0], -fx);
-      atomicAdd(&S.g[j][1], -fy);
-      atomicAdd(&S.g[j][2], -fz);
+  if (UNROLL == 1) {
+    for (int step = 0; step < n_steps; ++step) {
+      const int p = step * W + lane;
+      if (p >= L.n_pairs) continue;
+      const PairRec rec = rec_a;
+      const LJRec lj = lj_a;
+      rec_a = rec_b;
+      rec_b = pair_at(p + 2 * W);
+      lj_a = lj_of(rec_a);
+      do_pair(rec, lj, true);
     }
+  } else {
+    // Two steps per trip with fixed register roles: rec_a holds the record
+    // of the trip's first step and rec_b that of its second, each reloaded
+    // in place two steps ahead, so no record is moved between registers
+    // (a move of a record still in flight would wait for its load).  Every
+    // step but the last covers whole groups, so only the second step of a
+    // trip and a final odd step mask lanes; the second step computes on every
+    // lane and masks only its sum and forces, so its loads are issued a step
+    // ahead of their use.
+    int step = 0;
+    for (; step + 1 < n_steps; step += 2) {
+      const int p = step * W + lane;   // below n_pairs: not the last step
+      const PairRec c0 = rec_a;
+      const LJRec j0 = lj_a;
+      const LJRec lj_b = lj_of(rec_b);
+      rec_a = pair_at(p + 2 * W);
+      const PairRec c1 = rec_b;
+      // both steps' positions are read before the first step's force
+      // additions, which the LDS would otherwise serve first
+      const PairGeo g0 = pair_geo(c0), g1 = pair_geo(c1);
+      pair_terms(c0, j0, g0, true);
+      const int p1 = p + W;
+      const bool live = p1 < L.n_pairs;
+      rec_b = pair_at(live ? p1 + 2 * W : p);   // past the list: read a valid record, unused
+      lj_a = lj_of(rec_a);
+      pair_terms(c1, lj_b, g1, live);
+    }
+    if (step < n_steps && step * W + lane < L.n_pairs) do_pair(rec_a, lj_a, true);
   }
   // one wavefront sum unless the caller wants the two parts
   double total;
