@@ -96,15 +96,16 @@ std::vector<int> stage_candidates(const EvalConst &C, const DockArgs &D, int cap
 }
 
 // Launch schedule of one bucket's local search, chosen by timing: the shape
-// (pair-loop unroll 1 or 2; work-groups resident per CU: as many as the LDS
-// allows, three quarters or half of that, set by padding the dynamic LDS)
-// and the number of pair records staged in LDS.  Timing runs the bucket's
+// (pair loop one or two steps per trip; work-groups resident per CU: as many
+// as the LDS allows, three quarters or half of that, set by padding the
+// dynamic LDS), the persistent work queue (a bucket of one chain only) and
+// the number of pair records staged in LDS.  Timing runs the bucket's
 // local search (few iterations) from the evaluated initial population on a
 // copy of the population buffers, once per candidate (best of three), on a
 // strided sample of its runs; the docking state itself is not touched.
 // Every candidate computes bitwise the same values, so the choice affects
-// speed only.  A candidate replaces the default (unroll 1, full occupancy,
-// no staging) only if it is 3 % faster.  Forced values (ad_set_schedule,
+// speed only.  A candidate replaces the default (one step per trip, full
+// occupancy, no queue, no staging) only if it is 3 % faster.  Forced values (ad_set_schedule,
 // ad_set_launch_shape) are taken as given.
 constexpr int kLdsPerCU = 160 * 1024;
 constexpr int kMaxWgPerCU = 16;   // 4 one-wavefront work-groups per SIMD (the kernel's VGPR budget)
@@ -119,7 +120,7 @@ int pad_for(size_t lds, int target) {
 }
 
 int choose_schedule(ad_ctx *c, const ad_batch *b, const int *sel, int n_lig, const EvalConst &C, const DockArgs &Dk,
-                    int cap, int max_pairs, bool stage_ok, LsChoice *out) {
+                    int cap, int max_pairs, bool stage_ok, bool chained, LsChoice *out) {
   const int bk = cap > 64 ? 1 : 0;
   LsChoice best;
   best.stage = 0;
@@ -135,14 +136,18 @@ int choose_schedule(ad_ctx *c, const ad_batch *b, const int *sel, int n_lig, con
   best.queue = c->forced_queue > 0 ? 1 : 0;
   const bool tune_shape = c->autotune && (c->forced_unroll <= 0 || c->forced_wgcu <= 0);
   const bool tune_stage = c->autotune && c->forced_stage < 0 && stage_cand.size() > 1;
-  const bool tune_queue = c->autotune && c->forced_queue < 0;
+  // The queue's gain is a launch's tail, which a bucket split into several
+  // chains already fills from the other chains' launches; the timing sample
+  // (one launch of a part of the runs) shows the tail but not the chains, so
+  // the queue is tuned only for a bucket that runs as one chain.
+  const bool tune_queue = c->autotune && c->forced_queue < 0 && !chained;
   if (!tune_shape && !tune_stage && !tune_queue) {
     if (best.wg_per_cu <= 0) best.wg_per_cu = natural;
     *out = best;
     return AD_OK;
   }
   std::vector<int64_t> key = {(int64_t)b->uid, cap, Dk.pop, Dk.n_ls, Dk.n_launch, n_lig, Dk.n_dual,
-                              c->forced_unroll, c->forced_wgcu, c->forced_stage, c->forced_queue};
+                              c->forced_unroll, c->forced_wgcu, c->forced_stage, c->forced_queue, chained ? 1 : 0};
   if (sel) {
     uint64_t h = 1469598103934665603ull;
     for (int l = 0; l < n_lig; ++l) h = (h ^ (uint64_t)sel[l]) * 1099511628211ull;
@@ -515,9 +520,13 @@ int dock_impl(ad_ctx *c, const ad_batch *b, int n_lig, const int *sel, const ad_
     } else if (do_ls) {
       // packed runs stage no pairs; their launch still takes the tuned shape
       bool stage_ok = true;
+      int bk_chains = 0;
       for (const Chain &x : chains)
-        if (x.bk == bk && x.n_dual > 0) stage_ok = false;
-      rc = choose_schedule(c, b, sel, n_lig, C, chains[first].D, cap_b, max_pairs[bk], stage_ok, &ch);
+        if (x.bk == bk) {
+          ++bk_chains;
+          if (x.n_dual > 0) stage_ok = false;
+        }
+      rc = choose_schedule(c, b, sel, n_lig, C, chains[first].D, cap_b, max_pairs[bk], stage_ok, bk_chains > 1, &ch);
       if (rc) return rc;
       tuned = true;
       c->last_stage[bk] = ch.stage;
