@@ -175,9 +175,11 @@ def test_schedules_give_identical_results(pkg, setup):
     ctx, grid, G = setup
     # sizes across both buckets and the packing limit; large pair lists make
     # lanes of different steps add to the same atoms (where an order change
-    # between schedules would show in the last bits)
+    # between schedules would show in the last bits).  The pair-step counts
+    # cover one step, odd and even counts, and last steps from 1 to 62 live
+    # lanes, on 32-lane halves (packed) and whole wavefronts
     sizes = [(12, 2), (30, 7), (70, 20), (50, 12), (90, 25), (20, 5), (40, 10), (60, 16), (64, 24), (100, 30),
-             (33, 8), (45, 13), (128, 32), (58, 14)]
+             (33, 8), (45, 13), (128, 32), (58, 14), (28, 7)]
     ligs = [synth.ligand(70 + i, n, t) for i, (n, t) in enumerate(sizes)]
     batch = ctx.ad_load_ligands(ligs)
     p = small_params(pkg, ls_iters=30, max_gens=5)
