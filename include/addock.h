@@ -372,19 +372,23 @@ int ad_set_schedule(ad_ctx *ctx, int use_graph, int autotune, int stage_pairs, i
  * packed_runs: runs whose local search was packed (any may be null). */
 int ad_get_schedule(ad_ctx *ctx, int *stage_pairs, int *graph_used, int *packed_runs);
 
-/* Launch shape of the ADADELTA local-search kernel, per bucket (the target
- * configuration's batching: work-group shape and pair-list tiling chosen by
+/* Launch shape of the ADADELTA local-search kernel, per bucket (batching of
+ * uneven ligands, Sec. 2.2: work-group residency and pair-loop form chosen by
  * the library's autotuner per atom-count bucket).  Two dimensions, both
  * changing speed only (bitwise the same results):
- *   unroll     the pair loop handles 1 or 2 of each lane's pairs per
- *              iteration (each lane still adds its pairs in list order);
+ *   unroll     1: the pair loop takes one step (a pair per lane) per trip;
+ *              2: two steps per trip, both steps' records held in fixed
+ *              registers and both steps' positions read before the first
+ *              step's force additions (each lane still adds its pairs in
+ *              list order);
  *   wg_per_cu  one-wavefront work-groups resident per compute unit: as many
  *              as the kernel's LDS allows (at most 16), or fewer by padding
  *              the dynamic LDS (fewer individuals share a CU's caches).
  * With autotune (ad_set_schedule) each dock call's buckets time unroll
  * {1, 2} x wg_per_cu {all, 3/4, 1/2 of what fits} on a sample of their runs
- * (cached per batch and call shape), then the pair-staging sizes; a
- * candidate replaces the default only if it is 3 % faster.
+ * (cached per batch and call shape), then the work queue (ad_set_work_queue),
+ * then the pair-staging sizes; a candidate replaces the default only if it
+ * is 3 % faster.
  * ad_set_launch_shape forces unroll (1 or 2) and/or wg_per_cu (1..64, capped
  * at what fits); 0 leaves a dimension to the tuner (the default).
  * ad_get_launch_shape: unroll[2] and wg_per_cu[2] used per bucket (<= 64,
@@ -402,8 +406,10 @@ int ad_get_launch_shape(ad_ctx *ctx, int *unroll, int *wg_per_cu);
  * ticket counter until none is left; items of runs that have stopped
  * (autostop, Solis-Wets) are skipped without a dispatch.  Results are
  * bitwise the same either way.  mode: -1 the autotuner times the ADADELTA
- * local search both ways and keeps the queue only if it is 3 % faster (the
- * default), 0 off, 1 on; the GA launches follow the bucket's choice (with
+ * local search both ways and keeps the queue only if it is 3 % faster, for a
+ * bucket that runs as one chain (ad_set_chains; a bucket split into chains
+ * keeps the queue off: the other chains' launches fill a launch's tail, the
+ * queue's only gain) (the default), 0 off, 1 on; the GA launches follow the bucket's choice (with
  * Solis-Wets, whose launches stay one work-group per item, they follow a
  * forced 1).  The ticket counters live in the docking state and are cleared
  * once per dock call, before any launch.  ad_get_work_queue: used[2], the

@@ -375,7 +375,7 @@ class Context:
         return dict(stage_pairs=[st[0], st[1]], graph=bool(g.value), packed_runs=pk.value)
 
     def ad_set_launch_shape(self, unroll=0, wg_per_cu=0):
-        """Force the local search's pair-loop unroll (1, 2) and/or work-groups per CU; 0: tuned."""
+        """Force the local search's pair-loop form (1 or 2 steps per trip) and/or work-groups per CU; 0: tuned."""
         self._check(lib().ad_set_launch_shape(self.h, int(unroll), int(wg_per_cu)))
 
     def ad_get_launch_shape(self):
