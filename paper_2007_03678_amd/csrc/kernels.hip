@@ -1072,7 +1072,7 @@ __device__ __forceinline__ void ga_item(const EvalConst &C, const DockArgs &D, i
   const float g = round_gene(gene);
   if (lane < kStride) S.geno[lane] = (double)g;
   __syncthreads();
-  const double E = evaluate<CAP, false>(C, LL, S, lane, nullptr, nullptr);
+  const double E = evaluate<CAP, false, false, 64, kMaxTor, 2>(C, LL, S, lane, nullptr, nullptr);
   if (lane < kStride) newG[(size_t)i * kStride + lane] = g;
   if (lane == 0) {
     newE[i] = (float)E;
@@ -1302,7 +1302,7 @@ __device__ int sw_wave(const EvalConst &C, const LaneLig<CAP> &LL, EvalLds<CAP> 
     float cand = sw_moved(gene, step, 1.0f, lane, T);
     if (lane < kStride) S.geno[lane] = (double)cand;
     __syncthreads();
-    double E = evaluate<CAP, false>(C, LL, S, lane, nullptr, nullptr);
+    double E = evaluate<CAP, false, false, 64, kMaxTor, 2>(C, LL, S, lane, nullptr, nullptr);
     ++ev;
     if (E < Ex) {
       gene = cand;
@@ -1314,7 +1314,7 @@ __device__ int sw_wave(const EvalConst &C, const LaneLig<CAP> &LL, EvalLds<CAP> 
       __syncthreads();
       if (lane < kStride) S.geno[lane] = (double)cand;
       __syncthreads();
-      E = evaluate<CAP, false>(C, LL, S, lane, nullptr, nullptr);
+      E = evaluate<CAP, false, false, 64, kMaxTor, 2>(C, LL, S, lane, nullptr, nullptr);
       ++ev;
       if (E < Ex) {
         gene = cand;
@@ -1412,7 +1412,7 @@ __global__ __launch_bounds__(64) void k_solis_wets(EvalConst C, DockArgs D, int 
   }
   if (lane < kStride) S.geno[lane] = (double)g[lane];
   __syncthreads();
-  const double E0 = evaluate<CAP, false>(C, LL, S, lane, nullptr, nullptr);
+  const double E0 = evaluate<CAP, false, false, 64, kMaxTor, 2>(C, LL, S, lane, nullptr, nullptr);
   __syncthreads();
   if (lane == 0) E[p] = (float)E0;
   __syncthreads();
